@@ -1,0 +1,346 @@
+"""ctypes front end of the FP64 CPU oracle (rich_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+
+Takes the plain scene / source dictionaries of ``paper_2309_12496_amd.inputs``
+and returns numpy arrays in float64.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborcl.so")
+MAX_TABLE = 32
+
+DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES = range(6)
+SRC_TRACK, SRC_BATCH, SRC_EXPLICIT = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("n_mat", C.c_int32), ("mat_kind", _ip), ("mat_nrefl", _ip), ("mat_refl_x", _dp), ("mat_refl_y", _dp),
+        ("n_seg", C.c_int32), ("seg_pivot", _dp), ("seg_u0", _dp), ("seg_e1", _dp), ("seg_e2", _dp),
+        ("seg_r0", _dp), ("params", _dp),
+        ("n_cap", C.c_int32), ("cap_seg", _ip), ("cap_mat", _ip), ("cap_origin", _dp), ("cap_a", _dp),
+        ("cap_b", _dp), ("cap_bounds", _dp),
+        ("n_rect", C.c_int32), ("rect_mat", _ip), ("rect_c", _dp), ("rect_n", _dp), ("rect_u", _dp),
+        ("rect_v", _dp), ("rect_half", _dp),
+        ("n_tri", C.c_int64), ("tri_v", _dp), ("tri_mat", _ip), ("tri_seg", _ip),
+        ("det_c", C.c_double * 3), ("det_n", C.c_double * 3), ("det_u", C.c_double * 3), ("det_v", C.c_double * 3),
+        ("det_half", C.c_double * 2), ("det_pitch", C.c_double),
+        ("det_nx", C.c_int32), ("det_ny", C.c_int32), ("n_qe", C.c_int32),
+        ("qe_x", C.c_double * MAX_TABLE), ("qe_y", C.c_double * MAX_TABLE),
+        ("has_box", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+        ("max_bounces", C.c_int32), ("t_min", C.c_double),
+    ]
+
+
+class Source(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("origin", C.c_double * 3), ("dir", C.c_double * 3), ("length", C.c_double), ("beta", C.c_double),
+        ("n_tracks", C.c_int64), ("tracks", _dp), ("offsets", C.POINTER(C.c_uint64)),
+        ("ex_o", _dp), ("ex_d", _dp), ("ex_lambda", _dp),
+        ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+    ]
+
+
+class Outputs(C.Structure):
+    _fields_ = [
+        ("fate", C.POINTER(C.c_uint8)), ("pixel", _ip), ("hit_xyz", _dp), ("hit_uv", _dp),
+        ("edge_margin", _dp), ("pixel_margin", _dp), ("roulette_margin", _dp), ("n_bounce", _ip), ("segment", _ip), ("jac", _dp),
+    ]
+
+
+def build(force=True):
+    """Compile the oracle with gcc: -O2, IEEE double arithmetic, no fast-math."""
+    src = os.path.join(HERE, "rich_oracle.c")
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(src):
+        return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+           "-Wall", "-Wno-unused-function", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_scene_create.restype = C.c_void_p
+        L.orc_scene_create.argtypes = [C.POINTER(SceneDesc), C.c_int]
+        L.orc_scene_free.argtypes = [C.c_void_p]
+        L.orc_last_error.restype = C.c_char_p
+        L.orc_propagate.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint64,
+                                    C.c_int, C.c_int, C.c_int, C.POINTER(Outputs)]
+        L.orc_generate.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint64,
+                                   _dp, _dp, _dp]
+        L.orc_closest_hit.argtypes = [C.c_void_p, C.c_uint64, _dp, _dp, C.c_int,
+                                      C.POINTER(C.c_int64), _dp]
+        L.orc_prim_base_triangles.restype = C.c_int64
+        L.orc_prim_base_triangles.argtypes = [C.c_void_p]
+        L.orc_philox4x32_r.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int,
+                                       C.POINTER(C.c_uint32)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def philox(ctr, key, rounds=10):
+    """Philox4x32 block of four 32-bit words."""
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_r(c, k, rounds, o)
+    return [int(x) for x in o]
+
+
+class Scene:
+    """Oracle scene built from an ``inputs`` scene dict (optionally with other params)."""
+
+    def __init__(self, scene, params=None, bvh=True):
+        self._keep = []
+        d = SceneDesc()
+        mats = scene["materials"]
+        nm = len(mats)
+        kind = np.array([m["kind"] for m in mats], np.int32)
+        nref = np.array([len(m["refl_lambda"]) for m in mats], np.int32)
+        rx = np.zeros((max(nm, 1), MAX_TABLE))
+        ry = np.zeros((max(nm, 1), MAX_TABLE))
+        for i, m in enumerate(mats):
+            rx[i, :len(m["refl_lambda"])] = m["refl_lambda"]
+            ry[i, :len(m["refl_value"])] = m["refl_value"]
+        d.n_mat = nm
+        d.mat_kind = self._i(kind)
+        d.mat_nrefl = self._i(nref)
+        d.mat_refl_x = self._d(rx)
+        d.mat_refl_y = self._d(ry)
+
+        sg = scene["segments"]
+        p = np.asarray(scene["params"] if params is None else params, np.float64).reshape(-1, 6)
+        d.n_seg = len(sg["radius0"])
+        d.seg_pivot = self._d(sg["pivot"])
+        d.seg_u0 = self._d(sg["u0"])
+        d.seg_e1 = self._d(sg["e1"])
+        d.seg_e2 = self._d(sg["e2"])
+        d.seg_r0 = self._d(sg["radius0"])
+        d.params = self._d(p)
+
+        cp = scene["caps"]
+        d.n_cap = len(cp["segment"])
+        d.cap_seg = self._i(cp["segment"])
+        d.cap_mat = self._i(cp["material"])
+        d.cap_origin = self._d(cp["origin"])
+        d.cap_a = self._d(cp["axis_a"])
+        d.cap_b = self._d(cp["axis_b"])
+        d.cap_bounds = self._d(cp["bounds"])
+
+        rc = scene["rects"]
+        d.n_rect = len(rc["material"])
+        d.rect_mat = self._i(rc["material"])
+        d.rect_c = self._d(rc["center"])
+        d.rect_n = self._d(rc["normal"])
+        d.rect_u = self._d(rc["axis_u"])
+        d.rect_v = self._d(rc["axis_v"])
+        d.rect_half = self._d(rc["half"])
+
+        meshes = scene["meshes"]
+        if meshes:
+            tv = np.concatenate([m["vertices"].reshape(-1, 9) for m in meshes], axis=0)
+            tm = np.concatenate([np.full(len(m["vertices"]), m["material"], np.int32) for m in meshes])
+            ts = np.concatenate([np.full(len(m["vertices"]), m["segment"], np.int32) for m in meshes])
+        else:
+            tv = np.zeros((0, 9))
+            tm = np.zeros(0, np.int32)
+            ts = np.zeros(0, np.int32)
+        d.n_tri = len(tv)
+        d.tri_v = self._d(tv)
+        d.tri_mat = self._i(tm)
+        d.tri_seg = self._i(ts)
+
+        det = scene["detector"]
+        d.det_c[:] = list(det["center"])
+        d.det_n[:] = list(det["normal"])
+        d.det_u[:] = list(det["axis_u"])
+        d.det_v[:] = list(det["axis_v"])
+        d.det_half[:] = list(det["half"])
+        d.det_pitch = float(det["pitch"])
+        d.det_nx = int(det["nx"])
+        d.det_ny = int(det["ny"])
+        d.n_qe = len(det["qe_lambda"])
+        for i in range(d.n_qe):
+            d.qe_x[i] = float(det["qe_lambda"][i])
+            d.qe_y[i] = float(det["qe_value"][i])
+        box = scene["box"]
+        d.has_box = 0 if box is None else 1
+        if box is not None:
+            d.box_lo[:] = list(box["lo"])
+            d.box_hi[:] = list(box["hi"])
+        d.max_bounces = int(scene["max_bounces"])
+        d.t_min = float(scene["t_min"])
+        self.desc = d
+        self.n_tri = int(d.n_tri)
+        self.handle = lib().orc_scene_create(C.byref(d), 1 if bvh else 0)
+        if not self.handle:
+            raise ValueError(lib().orc_last_error().decode())
+        self.has_bvh = bvh
+        self.tri_base = lib().orc_prim_base_triangles(self.handle)
+        self._keep = []     # the oracle copies every array at creation
+
+    def _d(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self._keep.append(a)
+        return _ptr(a, C.c_double)
+
+    def _i(self, a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        self._keep.append(a)
+        return _ptr(a, C.c_int32)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib().orc_scene_free(h)
+            self.handle = None
+
+
+def _source(src, keep):
+    s = Source()
+    kind = src["kind"]
+    s.n_radiator = float(src.get("n_radiator", 1.0))
+    s.lambda_min = float(src.get("lambda_min", 200.0))
+    s.lambda_max = float(src.get("lambda_max", 600.0))
+    if kind == "track":
+        s.kind = SRC_TRACK
+        s.origin[:] = list(src["origin"])
+        s.dir[:] = list(src["direction"])
+        s.length = float(src["length"])
+        s.beta = float(src["beta"])
+    elif kind == "batch":
+        s.kind = SRC_BATCH
+        tr = np.ascontiguousarray(src["tracks"], np.float64)
+        of = np.ascontiguousarray(src["offsets"], np.uint64)
+        keep += [tr, of]
+        s.n_tracks = len(tr)
+        s.tracks = _ptr(tr, C.c_double)
+        s.offsets = _ptr(of, C.c_uint64)
+    elif kind == "explicit":
+        s.kind = SRC_EXPLICIT
+        for name, field in (("o", "ex_o"), ("d", "ex_d"), ("lambda", "ex_lambda")):
+            a = np.ascontiguousarray(src[name], np.float64)
+            keep.append(a)
+            setattr(s, field, _ptr(a, C.c_double))
+    else:
+        raise ValueError(kind)
+    return s
+
+
+def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, threads=None):
+    """Trace photons first_id .. first_id+n-1; returns a dict of numpy arrays."""
+    if not isinstance(scene, Scene):
+        scene = Scene(scene, bvh=use_bvh)
+    keep = []
+    s = _source(src, keep)
+    n = int(n)
+    res = {
+        "fate": np.zeros(n, np.uint8), "pixel": np.zeros(n, np.int32),
+        "hit_xyz": np.zeros((n, 3)), "hit_uv": np.zeros((n, 2)),
+        "edge_margin": np.zeros(n), "pixel_margin": np.zeros(n), "roulette_margin": np.zeros(n), "n_bounce": np.zeros(n, np.int32),
+    }
+    o = Outputs()
+    o.fate = _ptr(res["fate"], C.c_uint8)
+    o.pixel = _ptr(res["pixel"], C.c_int32)
+    o.hit_xyz = _ptr(res["hit_xyz"], C.c_double)
+    o.hit_uv = _ptr(res["hit_uv"], C.c_double)
+    o.edge_margin = _ptr(res["edge_margin"], C.c_double)
+    o.pixel_margin = _ptr(res["pixel_margin"], C.c_double)
+    o.roulette_margin = _ptr(res["roulette_margin"], C.c_double)
+    o.n_bounce = _ptr(res["n_bounce"], C.c_int32)
+    if jacobian:
+        res["segment"] = np.zeros(n, np.int32)
+        res["jac"] = np.zeros((n, 2, 6))
+        o.segment = _ptr(res["segment"], C.c_int32)
+        o.jac = _ptr(res["jac"], C.c_double)
+    if threads is None:
+        threads = min(os.cpu_count() or 1, 16)
+    rc = lib().orc_propagate(scene.handle, C.byref(s), n, int(seed), int(first_id),
+                             1 if (use_bvh and scene.has_bvh) else 0, 1 if jacobian else 0, int(threads),
+                             C.byref(o))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return res
+
+
+def generate(src, n, seed, first_id=0, scene=None):
+    """Generated photon origins, directions and wavelengths (no tracing)."""
+    keep = []
+    s = _source(src, keep)
+    o = np.zeros((n, 3))
+    d = np.zeros((n, 3))
+    lam = np.zeros(n)
+    lib().orc_generate(None, C.byref(s), int(n), int(seed), int(first_id),
+                       _ptr(o, C.c_double), _ptr(d, C.c_double), _ptr(lam, C.c_double))
+    return o, d, lam
+
+
+def closest_hit(scene, o, d, use_bvh=True):
+    o = np.ascontiguousarray(o, np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    prim = np.zeros(len(o), np.int64)
+    t = np.zeros(len(o))
+    lib().orc_closest_hit(scene.handle, len(o), _ptr(o, C.c_double), _ptr(d, C.c_double),
+                          1 if use_bvh else 0, _ptr(prim, C.c_int64), _ptr(t, C.c_double))
+    return prim, t
+
+
+def histogram(res, nx, ny):
+    """Pixel histogram of DETECTED photons (derived by counting)."""
+    px = res["pixel"][res["fate"] == DETECTED]
+    return np.bincount(px, minlength=nx * ny).astype(np.uint32)
+
+
+def fate_counts(res):
+    return np.bincount(res["fate"], minlength=6).astype(np.uint64)
+
+
+def mse_loss_and_grad(res, targets, mask, n_seg):
+    """Masked mean squared hit residual and its gradient through the oracle Jacobians.
+
+    L = (1/N) sum_i |uv_i - target_i|^2 over photons in ``mask`` that reach the
+    detector; dL/dp = (2/N) sum_i J_i^T (uv_i - target_i) scattered to each
+    photon's segment.
+    """
+    use = mask.astype(bool) & np.isin(res["fate"], [DETECTED, QE_REJECTED])
+    if np.any(res["segment"][use] == -2):
+        raise ValueError("a masked photon hits two parametrised segments; its Jacobian is not tracked")
+    nuse = int(use.sum())
+    grad = np.zeros((n_seg, 6))
+    if nuse == 0:
+        return 0.0, grad, 0
+    r = res["hit_uv"][use] - targets[use]
+    loss = float((r * r).sum() / nuse)
+    seg = res["segment"][use]
+    has = seg >= 0
+    contrib = np.einsum("nk,nkp->np", r[has], res["jac"][use][has]) * (2.0 / nuse)
+    np.add.at(grad, seg[has], contrib)
+    return loss, grad, nuse

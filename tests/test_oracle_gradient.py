@@ -1,0 +1,140 @@
+"""Pins of the oracle's hit-position Jacobians with respect to the mirror-segment parameters.
+
+The oracle carries forward-mode dual numbers along each photon's path.  They
+are pinned against central finite differences of the oracle's own FP64 hit
+positions (a different computation: two full re-traces with moved segments)
+and, for analytic spherical segments, against the chain-rule invariant that
+interior hits depend on a segment only through its sphere centre C and radius
+R: dX/dtilt = dX/dC . dC/dtilt, with dC/dtilt_x = R e1 x u0 at zero tilt.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2309_12496_amd import inputs as I
+
+H = np.array([1e-6, 1e-6, 1e-3, 1e-3, 1e-3, 1e-3])      # rad, rad, mm, mm, mm, mm
+
+
+def _c4_small(n_tracks=80, per_track=100):
+    rng = np.random.default_rng(1004)
+    src = I.batch_source(I.sample_tracks(rng, n_tracks), np.full(n_tracks, per_track))
+    return I.scene_g4(), src, n_tracks * per_track
+
+
+def _fd_jacobian(orc, scene, src, n, seed, params, seg_of_photon, H=H):
+    """Central differences of every photon's (u, v) for each parameter of its own segment."""
+    J = np.full((n, 2, 6), np.nan)
+    nseg = params.shape[0]
+    for k in range(nseg):
+        mine = seg_of_photon == k
+        if not mine.any():
+            continue
+        for m in range(6):
+            pp = params.copy()
+            pm = params.copy()
+            pp[k, m] += H[m]
+            pm[k, m] -= H[m]
+            rp = orc.propagate(orc.Scene(scene, params=pp), src, n, seed)
+            rm = orc.propagate(orc.Scene(scene, params=pm), src, n, seed)
+            J[mine, :, m] = ((rp["hit_uv"] - rm["hit_uv"]) / (2 * H[m]))[mine]
+    return J
+
+
+@pytest.mark.parametrize("perturbed", [False, True])
+def test_dual_jacobian_matches_central_differences_analytic(orc, perturbed):
+    scene, src, n = _c4_small()
+    params = I.perturbed_params(4, scene) if perturbed else scene["params"].copy()
+    seed = I.SEED_BASE + 4
+    res = orc.propagate(orc.Scene(scene, params=params), src, n, seed, jacobian=True)
+    on = np.isin(res["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (res["edge_margin"] > 1.0) & (res["segment"] >= 0)
+    assert on.sum() > 300
+    # with a 600 mm detector only the four central segments send light onto it
+    assert len(np.unique(res["segment"][on])) >= 4
+    seg = np.where(on, res["segment"], -1)
+    Jfd = _fd_jacobian(orc, scene, src, n, seed, params, seg)
+    Jd = res["jac"][on]
+    Jf = Jfd[on]
+    scale = np.abs(Jd).max(axis=(0, 1))
+    err = np.abs(Jd - Jf).max(axis=(0, 1)) / scale
+    assert np.all(err < 1e-5), err
+
+
+@pytest.mark.parametrize("perturbed", [False, True])
+def test_tilt_columns_follow_centre_columns(orc, perturbed):
+    """dX/dtilt = dX/ddelta . dC/dtilt for spherical segments (interior hits see only C and R)."""
+    scene, src, n = _c4_small()
+    params = I.perturbed_params(4, scene) if perturbed else scene["params"].copy()
+    res = orc.propagate(orc.Scene(scene, params=params), src, n, I.SEED_BASE + 4, jacobian=True)
+    on = np.isin(res["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (res["segment"] >= 0)
+    seg = res["segment"][on]
+    J = res["jac"][on]
+    sg = scene["segments"]
+
+    def rot(k, th, v):
+        k = k / np.linalg.norm(k)
+        return v * np.cos(th) + np.cross(k, v) * np.sin(th) + k * (k @ v) * (1 - np.cos(th))
+
+    for kseg in np.unique(seg):
+        sel = seg == kseg
+        tx, ty, R = params[kseg, :3]
+        e1, e2, u0 = sg["e1"][kseg], sg["e2"][kseg], sg["u0"][kseg]
+        dC_dtx = R * rot(e2, ty, np.cross(e1, rot(e1, tx, u0)))
+        dC_dty = R * np.cross(e2, rot(e2, ty, rot(e1, tx, u0)))
+        Jd = J[sel][:, :, 3:6]
+        assert np.allclose(J[sel][:, :, 0], Jd @ dC_dtx, rtol=1e-9, atol=1e-9 * np.abs(J[sel][:, :, 0]).max())
+        assert np.allclose(J[sel][:, :, 1], Jd @ dC_dty, rtol=1e-9, atol=1e-9 * np.abs(J[sel][:, :, 1]).max())
+
+
+def test_loss_gradient_matches_central_differences(orc):
+    """Masked MSE of hit residuals against targets from misaligned segments."""
+    scene, src, n = _c4_small(100, 100)
+    seed = I.SEED_BASE + 4
+    tgt_params = I.perturbed_params(4, scene)
+    target = orc.propagate(orc.Scene(scene, params=tgt_params), src, n, seed)
+    p0 = scene["params"].copy()
+    cur = orc.propagate(orc.Scene(scene, params=p0), src, n, seed, jacobian=True)
+    on_det = lambda r: np.isin(r["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    mask = on_det(target) & on_det(cur) & (target["edge_margin"] > 1.0) & (cur["edge_margin"] > 1.0)
+    assert mask.sum() > 100
+    loss, grad, nuse = orc.mse_loss_and_grad(cur, target["hit_uv"], mask, p0.shape[0])
+    assert nuse == mask.sum() and loss > 0
+
+    def L(p):
+        r = orc.propagate(orc.Scene(scene, params=p), src, n, seed)
+        assert np.all(np.isin(r["fate"][mask], [orc.DETECTED, orc.QE_REJECTED]))
+        d = r["hit_uv"][mask] - target["hit_uv"][mask]
+        return (d * d).sum() / mask.sum()
+
+    assert abs(L(p0) - loss) < 1e-12 * loss
+    for k in np.unique(cur["segment"][mask])[:4]:
+        for m in range(6):
+            pp = p0.copy()
+            pm = p0.copy()
+            pp[k, m] += H[m]
+            pm[k, m] -= H[m]
+            fd = (L(pp) - L(pm)) / (2 * H[m])
+            assert abs(fd - grad[k, m]) <= 1e-5 * max(abs(grad[k]).max(), 1e-12), (k, m, fd, grad[k, m])
+
+
+def test_meshed_segment_jacobian_matches_central_differences(orc):
+    """Facet hits on rigidly moved and scaled meshed segments (small meshes for speed)."""
+    scene = I.scene_g5(seg_quads=(14, 23), flat_tiles=2, n_pix=512)
+    rng = np.random.default_rng(1005)
+    src = I.batch_source(I.sample_tracks(rng, 80), np.full(80, 60))
+    n = 4800
+    seed = I.SEED_BASE + 5
+    params = I.perturbed_params(5, scene)
+    res = orc.propagate(orc.Scene(scene, params=params), src, n, seed, jacobian=True)
+    on = (np.isin(res["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (res["edge_margin"] > 0.05)
+          & (res["segment"] >= 0))
+    assert on.sum() > 200
+    seg = np.where(on, res["segment"], -1)
+    # scaling about the pivot leaves facet normals unchanged, so dX/dR is ~1e-5 and needs a
+    # 1 mm step to rise above the ~1e-9 mm rounding noise of FP64 facet normals
+    Jfd = _fd_jacobian(orc, scene, src, n, seed, params, seg, H=np.array([1e-6, 1e-6, 1.0, 1e-3, 1e-3, 1e-3]))
+    Jd = res["jac"][on]
+    Jf = Jfd[on]
+    scale = np.abs(Jd).max(axis=(0, 1))
+    err = np.abs(Jd - Jf).max(axis=(0, 1)) / scale
+    assert np.all(err < 1e-4), err
