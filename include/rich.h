@@ -1,0 +1,292 @@
+/*
+ * rich.h - C ABI of librich.so: Cherenkov optical-photon propagation through a
+ * RICH-like detector on AMD MI355X (gfx950).
+ *
+ * What the calls compute comes from arxiv 2309.12496 ("Optical Photon
+ * Simulation with Mitsuba3"):
+ *   - photons are emitted on the Cherenkov cone cos(theta) = 1/(n beta),
+ *     azimuth-independent (Section 3), or handed over one by one as origin,
+ *     direction and wavelength arrays (Section 4.2, the photon emitter);
+ *   - they fly straight through a scene reduced to mirrors, absorbing walls
+ *     and a detector plane (Section 4.1, windows and casing removed);
+ *   - mirror reflectivity and detector quantum efficiency depend on the
+ *     wavelength (Section 4.3) and are applied where the photon meets the
+ *     surface, the kill-or-propagate treatment proposed in Section 7;
+ *   - detected photons are reported as global hit coordinates and pixel ids
+ *     (Section 4.4), optionally as a compact list of hits (Section 7).
+ * rich_propagate_batch and rich_propagate_adjoint extend the paper: one
+ * persistent launch over many tracks, and the reverse-mode derivative of the
+ * detector hits with respect to mirror-segment alignment parameters.
+ *
+ * Units: mm, nm, rad.  Conventions shared by every call:
+ *   - Pointers named dev_* are device pointers owned by the caller.  A scene
+ *     is owned by the library (rich_build_scene / rich_destroy_scene).
+ *   - Every call returns a rich_status.  No C++ exception crosses the ABI.
+ *     rich_last_error() returns a thread-local message for the last failure.
+ *   - Argument checks are synchronous; the propagation work is enqueued on
+ *     the given stream and returns immediately.  Flags raised on the device
+ *     (hit-list or traversal-stack overflow) are read by rich_get_status.
+ *   - NULL output pointers mean "do not write".  The histogram, fate counts
+ *     and hit-list counter accumulate: the caller zeroes them.
+ *   - A call on a stream that another thread uses concurrently with the same
+ *     scene is the caller's business; calls on one scene from one stream are
+ *     ordered.
+ */
+#ifndef RICH_H
+#define RICH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rich_status;
+#define RICH_OK         0
+#define RICH_EINVAL    -1   /* bad argument: NaN, n*beta <= 1, bad table, bad sizes */
+#define RICH_ENOMEM    -2   /* host or device allocation failed */
+#define RICH_EDEVICE   -3   /* HIP runtime error */
+#define RICH_ERANGE    -4   /* photon id range beyond 2^64 or beyond the batch */
+#define RICH_EOVERFLOW -5   /* device flag: hit list or traversal stack overflowed */
+#define RICH_ESTATE    -6   /* wrong call order (e.g. no parameters to differentiate) */
+
+/* Photon fates (per-photon output). */
+#define RICH_DETECTED        0   /* reached the detector front inside the pixel grid and passed QE */
+#define RICH_QE_REJECTED     1   /* reached the pixel grid but failed the QE roulette */
+#define RICH_ABSORBED_MIRROR 2   /* failed a mirror reflectivity roulette */
+#define RICH_ABSORBED        3   /* absorber, back face, or detector dead border */
+#define RICH_ESCAPED         4   /* left the scene without hitting anything */
+#define RICH_MAX_BOUNCES     5   /* still flying after max_bounces surfaces */
+#define RICH_N_FATES         6
+
+/* Device status flags returned by rich_get_status. */
+#define RICH_FLAG_HITLIST_OVERFLOW 0x1u
+#define RICH_FLAG_STACK_OVERFLOW   0x2u
+#define RICH_FLAG_PATH_OVERFLOW    0x4u   /* adjoint: more surfaces than it records */
+
+#define RICH_MAX_TABLE 32           /* nodes of a piecewise-linear efficiency table */
+#define RICH_MAX_SEGMENTS 256       /* parametrised mirror segments */
+
+#define RICH_MAT_MIRROR   0
+#define RICH_MAT_ABSORBER 1
+
+/* ---------------------------------------------------------------- scene ---- */
+
+/* Material: mirrors reflect with probability refl(lambda), a piecewise-linear
+ * table clamped to its end values (Section 4.3); absorbers end the photon. */
+typedef struct rich_material {
+    int32_t kind;                 /* RICH_MAT_MIRROR or RICH_MAT_ABSORBER */
+    int32_t n_refl;               /* 1..RICH_MAX_TABLE nodes, lambda increasing */
+    const double *refl_lambda;    /* host */
+    const double *refl_value;     /* host, in [0,1] */
+} rich_material;
+
+/* A parametrised mirror segment.  Its 6 parameters p = (tilt_x, tilt_y, R,
+ * dx, dy, dz) place a sphere of radius R with centre
+ *     C = pivot + (dx,dy,dz) + R * Rot(tilt_x, tilt_y) * u0,
+ * Rot = rotation about e2 by tilt_y after rotation about e1 by tilt_x.
+ * A meshed segment moves rigidly and scales about its pivot:
+ *     v = pivot + (dx,dy,dz) + Rot * (R/radius0) * (v_nominal - pivot). */
+typedef struct rich_segment {
+    double pivot[3];              /* a point of the nominal sphere */
+    double u0[3];                 /* unit vector pivot -> centre at zero tilt */
+    double e1[3], e2[3];          /* unit tilt axes, fixed */
+    double radius0;               /* nominal radius (scales meshed segments) */
+} rich_segment;
+
+/* Analytic spherical cap of a segment: the part of the segment's sphere on the
+ * pivot's side of the plane through C normal to Rot*u0, whose coordinates
+ * a = (P-origin).axis_a, b = (P-origin).axis_b lie in the half-open cell
+ * [bounds[0], bounds[1]) x [bounds[2], bounds[3]).  The active (reflecting)
+ * side is the concave one. */
+typedef struct rich_cap {
+    int32_t segment;              /* 0..n_segments-1 */
+    int32_t material;
+    double origin[3], axis_a[3], axis_b[3];
+    double bounds[4];
+} rich_cap;
+
+/* Flat rectangle |u| <= half[0], |v| <= half[1] about center; normal marks the active side. */
+typedef struct rich_rect {
+    int32_t material;
+    int32_t reserved;
+    double center[3], normal[3], axis_u[3], axis_v[3];
+    double half[2];
+} rich_rect;
+
+/* Triangle mesh.  The geometric normal (v1-v0)x(v2-v0) marks the active side.
+ * segment = -1: fixed; otherwise the mesh follows that segment's parameters. */
+typedef struct rich_mesh {
+    const double *vertices;       /* host [n_tri][3][3] */
+    int64_t n_tri;
+    int32_t material;
+    int32_t segment;
+} rich_mesh;
+
+/* Photodetector plane: a rectangle |u| <= half[0], |v| <= half[1]; the active
+ * side faces along normal.  Pixels of size pitch tile a centred nx*pitch by
+ * ny*pitch area; pixel = j*nx + i with i = floor((u + nx*pitch/2)/pitch).
+ * Hits outside the pixel grid are ABSORBED.  qe is a piecewise-linear table. */
+typedef struct rich_detector {
+    double center[3], normal[3], axis_u[3], axis_v[3];
+    double half[2];
+    double pitch;
+    int32_t nx, ny;
+    int32_t n_qe;
+    const double *qe_lambda;      /* host */
+    const double *qe_value;       /* host */
+} rich_detector;
+
+typedef struct rich_scene_desc {
+    int32_t n_materials;  const rich_material *materials;
+    int32_t n_segments;   const rich_segment *segments;
+    const double *params;         /* host [n_segments][6] initial parameters, or NULL = (0,0,radius0,0,0,0) */
+    int32_t n_caps;       const rich_cap *caps;
+    int32_t n_rects;      const rich_rect *rects;
+    int32_t n_meshes;     const rich_mesh *meshes;
+    rich_detector detector;
+    int32_t has_box;              /* 1: absorbing axis-aligned box surface */
+    double box_lo[3], box_hi[3];
+    int32_t max_bounces;          /* surfaces a photon may meet; 16 by default */
+    double t_min;                 /* self-intersection guard, mm (1e-2) */
+} rich_scene_desc;
+
+typedef struct rich_scene rich_scene;
+
+/* Scene statistics (rich_scene_info). */
+typedef struct rich_scene_stats {
+    int64_t n_triangles;
+    int64_t n_nodes;              /* BVH4 nodes, all instances plus the top level */
+    int32_t n_instances;
+    int32_t max_depth;            /* deepest BVH4 path, top level included */
+    int64_t device_bytes;
+    double build_seconds;         /* host time of rich_build_scene */
+} rich_scene_stats;
+
+/* --------------------------------------------------------------- sources ---- */
+
+#define RICH_SRC_TRACK    0       /* Cherenkov photons from a straight track segment (length 0: a point) */
+#define RICH_SRC_EXPLICIT 2       /* photons given one by one (Section 4.2) */
+
+typedef struct rich_source {
+    int32_t kind;
+    int32_t reserved;
+    /* RICH_SRC_TRACK: photon g is emitted at origin + s*length*dir, s uniform */
+    double origin[3], direction[3];
+    double length, beta;
+    /* RICH_SRC_EXPLICIT: device arrays indexed by g - first_photon_id */
+    const float *dev_o;           /* [N][3] */
+    const float *dev_d;           /* [N][3] unit */
+    const float *dev_lambda;      /* [N] nm */
+    /* spectrum and radiator (TRACK) */
+    double n_radiator, lambda_min, lambda_max;
+} rich_source;
+
+/* One track of a batch (32 bytes). */
+typedef struct rich_track {
+    float origin[3];
+    float direction[3];
+    float length;
+    float beta;
+} rich_track;
+
+/* Many tracks in one launch.  Track k owns global photon ids
+ * [offsets[k], offsets[k+1]); offsets is the exclusive scan of the counts. */
+typedef struct rich_batch {
+    const rich_track *dev_tracks; /* [n_tracks] */
+    const uint64_t *dev_offsets;  /* [n_tracks + 1], offsets[0] = 0 */
+    int32_t n_tracks;
+    int32_t reserved;
+    double n_radiator, lambda_min, lambda_max;
+} rich_batch;
+
+/* --------------------------------------------------------------- outputs ---- */
+
+typedef struct rich_hit {
+    uint64_t photon;              /* global photon id */
+    int32_t pixel;
+    float xyz[3];
+} rich_hit;
+
+/* Per-photon arrays are indexed by g - first_photon_id (batch: by g). */
+typedef struct rich_outputs {
+    uint8_t *fate;                /* [N] RICH_DETECTED.. */
+    int32_t *pixel;               /* [N] -1 unless DETECTED / QE_REJECTED */
+    float *hit_xyz;               /* [N][3] global hit, NaN unless DETECTED / QE_REJECTED */
+    float *hit_uv;                /* [N][2] detector coordinates, NaN likewise */
+    uint32_t *histogram;          /* [nx*ny] DETECTED photons per pixel, accumulated */
+    unsigned long long *fate_counts;  /* [RICH_N_FATES], accumulated */
+    rich_hit *hit_list;           /* [capacity] DETECTED photons, in no particular order */
+    uint64_t hit_list_capacity;
+    unsigned long long *hit_count;    /* [1] accumulated; may exceed capacity (flag raised) */
+} rich_outputs;
+
+/* Launch shape of the persistent batch kernel. */
+typedef struct rich_tuning {
+    int32_t block;                /* threads per block: 64, 128, 256 or 512 */
+    int32_t chunk;                /* photon ids fetched per wave at a time, multiple of 64 */
+    int32_t blocks_per_cu;        /* resident blocks per compute unit in the persistent grid */
+    int32_t reserved;
+} rich_tuning;
+
+/* ----------------------------------------------------------------- calls ---- */
+
+/* Build a scene on `device` from host FP64 data: validates, builds SAH BVH4s
+ * (one per mesh instance, in that instance's local frame, with facet normals
+ * computed in FP64) and a top-level BVH4, and uploads FP32 copies.
+ * Synchronous.  *out is NULL on failure. */
+rich_status rich_build_scene(const rich_scene_desc *desc, int device, rich_scene **out);
+rich_status rich_destroy_scene(rich_scene *s);
+rich_status rich_scene_info(const rich_scene *s, rich_scene_stats *out);
+
+/* Replace the segment parameters from a device array [n_segments][6] (FP32)
+ * and refresh the derived cap and instance data on the stream. */
+rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipStream_t stream);
+
+/* Propagate photons first_photon_id .. first_photon_id + n_photons - 1 of a
+ * single source, seeded by `seed` (Philox4x32-10, counter = photon id). */
+rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,
+                           uint64_t first_photon_id, const rich_outputs *out, hipStream_t stream);
+
+/* Propagate every photon of a batch (n_photons = offsets[n_tracks]) in one
+ * persistent launch replayed from a captured HIP graph.  tune = NULL picks the
+ * launch shape with the autotuner (cached per scene and in the JSON file named
+ * by RICH_TUNE_CACHE, if set). */
+rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
+                                 const rich_outputs *out, const rich_tuning *tune, hipStream_t stream);
+
+/* Time the batch kernel over a grid of launch shapes on scratch outputs and
+ * return the fastest (synchronous). */
+rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
+                          rich_tuning *out);
+
+/* Reverse-mode derivative of detector hit coordinates (u, v) with respect to
+ * the segment parameters, at the scene's current parameters, for the photons
+ * of either `src` (ids first_photon_id..) or `batch` (ids 0..), exactly one
+ * non-NULL.  Interior derivative: visibility changes at edges are ignored.
+ * Only photons with dev_mask[i] != 0 whose path ends on the pixel grid count.
+ *   dev_grad_uv != NULL: dev_grad_params = sum_i J_i^T dev_grad_uv[i];
+ *   dev_targets != NULL (fused loss): L = (1/N) sum_i |uv_i - target_i|^2 over
+ *     the N counted photons, dev_grad_params = dL/dp, *dev_loss = L.
+ * dev_grad_params [n_segments][6] is overwritten.  The sums are deterministic
+ * (fixed reduction order). */
+rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
+                                   uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
+                                   const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
+                                   float *dev_grad_params, float *dev_loss, hipStream_t stream);
+
+/* Synchronise the stream, return the device flags raised since the last call
+ * (RICH_FLAG_*) and clear them.  Returns RICH_EOVERFLOW when any is set. */
+rich_status rich_get_status(rich_scene *s, hipStream_t stream, uint32_t *flags);
+
+/* Thread-local description of the last error ("" if none). */
+const char *rich_last_error(void);
+
+/* Library version string. */
+const char *rich_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RICH_H */

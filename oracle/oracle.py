@@ -90,6 +90,8 @@ def lib():
         L.orc_last_error.restype = C.c_char_p
         L.orc_propagate.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint64,
                                     C.c_int, C.c_int, C.c_int, C.POINTER(Outputs)]
+        L.orc_propagate_ids.argtypes = [C.c_void_p, C.POINTER(Source), C.POINTER(C.c_uint64), C.c_uint64,
+                                        C.c_uint64, C.c_int, C.c_int, C.c_int, C.POINTER(Outputs)]
         L.orc_generate.argtypes = [C.c_void_p, C.POINTER(Source), C.c_uint64, C.c_uint64, C.c_uint64,
                                    _dp, _dp, _dp]
         L.orc_closest_hit.argtypes = [C.c_void_p, C.c_uint64, _dp, _dp, C.c_int,
@@ -255,17 +257,21 @@ def _source(src, keep):
     return s
 
 
-def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, threads=None):
-    """Trace photons first_id .. first_id+n-1; returns a dict of numpy arrays."""
+def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, threads=None, ids=None):
+    """Trace photons first_id .. first_id+n-1 (or the photon ids in ``ids``); returns numpy arrays."""
     if not isinstance(scene, Scene):
         scene = Scene(scene, bvh=use_bvh)
     keep = []
     s = _source(src, keep)
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        n = len(ids)
     n = int(n)
     res = {
         "fate": np.zeros(n, np.uint8), "pixel": np.zeros(n, np.int32),
         "hit_xyz": np.zeros((n, 3)), "hit_uv": np.zeros((n, 2)),
-        "edge_margin": np.zeros(n), "pixel_margin": np.zeros(n), "roulette_margin": np.zeros(n), "n_bounce": np.zeros(n, np.int32),
+        "edge_margin": np.zeros(n), "pixel_margin": np.zeros(n), "roulette_margin": np.zeros(n),
+        "n_bounce": np.zeros(n, np.int32),
     }
     o = Outputs()
     o.fate = _ptr(res["fate"], C.c_uint8)
@@ -283,9 +289,13 @@ def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, thr
         o.jac = _ptr(res["jac"], C.c_double)
     if threads is None:
         threads = min(os.cpu_count() or 1, 16)
-    rc = lib().orc_propagate(scene.handle, C.byref(s), n, int(seed), int(first_id),
-                             1 if (use_bvh and scene.has_bvh) else 0, 1 if jacobian else 0, int(threads),
-                             C.byref(o))
+    bvh = 1 if (use_bvh and scene.has_bvh) else 0
+    if ids is None:
+        rc = lib().orc_propagate(scene.handle, C.byref(s), n, int(seed), int(first_id), bvh, 1 if jacobian else 0,
+                                 int(threads), C.byref(o))
+    else:
+        rc = lib().orc_propagate_ids(scene.handle, C.byref(s), _ptr(ids, C.c_uint64), n, int(seed), bvh,
+                                     1 if jacobian else 0, int(threads), C.byref(o))
     if rc != 0:
         raise ValueError(lib().orc_last_error().decode())
     return res

@@ -722,6 +722,7 @@ typedef struct {
     const orc_scene *s;
     const orc_source *src;
     uint64_t n, seed, first_id;
+    const uint64_t *ids;       /* optional list of photon ids */
     int use_bvh, with_jac;
     const orc_outputs *out;
     uint64_t begin, end;
@@ -807,7 +808,7 @@ static void trace_photon(const job *jb, uint64_t i)
 {
     const orc_scene *s = jb->s;
     const orc_outputs *out = jb->out;
-    uint64_t g = jb->first_id + i;
+    uint64_t g = jb->ids ? jb->ids[i] : jb->first_id + i;
     photon ph;
     make_photon(jb->src, jb->seed, g, i, &ph);
     v3 o = ph.o, d = ph.d;
@@ -917,21 +918,25 @@ static void *run_job(void *arg)
     return NULL;
 }
 
-int orc_propagate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_t seed, uint64_t first_id,
-                  int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out)
+static int propagate_any(const orc_scene *s, const orc_source *src, const uint64_t *ids, uint64_t n, uint64_t seed,
+                         uint64_t first_id, int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out)
 {
     if (!s || !src || !out) { set_err("null argument"); return -1; }
+    if (ids && src->kind == ORC_SRC_EXPLICIT) { set_err("id lists need a generated source"); return -1; }
     if (src->kind != ORC_SRC_EXPLICIT) {
         if (!(src->n_radiator > 0) || !(src->lambda_min > 0) || !(src->lambda_max > src->lambda_min)) {
             set_err("bad source spectrum");
             return -1;
         }
-        double beta = src->kind == ORC_SRC_TRACK ? src->beta : 1.0;
-        if (src->kind == ORC_SRC_TRACK && !(src->n_radiator * beta > 1.0)) { set_err("n beta <= 1"); return -1; }
+        if (src->kind == ORC_SRC_TRACK && !(src->n_radiator * src->beta > 1.0)) { set_err("n beta <= 1"); return -1; }
         if (src->kind == ORC_SRC_BATCH) {
             for (int64_t k = 0; k < src->n_tracks; ++k)
                 if (!(src->n_radiator * src->tracks[8 * k + 7] > 1.0)) { set_err("n beta <= 1"); return -1; }
-            if (first_id + n > src->offsets[src->n_tracks]) { set_err("photon id beyond the batch"); return -1; }
+            uint64_t total = src->offsets[src->n_tracks];
+            if (!ids && first_id + n > total) { set_err("photon id beyond the batch"); return -1; }
+            if (ids)
+                for (uint64_t i = 0; i < n; ++i)
+                    if (ids[i] >= total) { set_err("photon id beyond the batch"); return -1; }
         }
     }
     if (n_threads < 1) n_threads = 1;
@@ -945,6 +950,7 @@ int orc_propagate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_
         jobs[k].n = n;
         jobs[k].seed = seed;
         jobs[k].first_id = first_id;
+        jobs[k].ids = ids;
         jobs[k].use_bvh = use_bvh;
         jobs[k].with_jac = with_jacobian;
         jobs[k].out = out;
@@ -960,4 +966,16 @@ int orc_propagate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_
     free(jobs);
     free(th);
     return 0;
+}
+
+int orc_propagate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_t seed, uint64_t first_id,
+                  int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out)
+{
+    return propagate_any(s, src, NULL, n, seed, first_id, use_bvh, with_jacobian, n_threads, out);
+}
+
+int orc_propagate_ids(const orc_scene *s, const orc_source *src, const uint64_t *ids, uint64_t n, uint64_t seed,
+                      int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out)
+{
+    return propagate_any(s, src, ids, n, seed, 0, use_bvh, with_jacobian, n_threads, out);
 }

@@ -125,6 +125,10 @@ int orc_propagate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_
                   uint64_t first_id, int use_bvh, int with_jacobian, int n_threads,
                   const orc_outputs *out);
 
+/* Same for an arbitrary list of photon ids (not for explicit sources); outputs indexed by list position. */
+int orc_propagate_ids(const orc_scene *s, const orc_source *src, const uint64_t *ids, uint64_t n, uint64_t seed,
+                      int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out);
+
 /* Closest hit of explicit rays (o, d) over the whole scene: prim index (-1 = none) and t. */
 int orc_closest_hit(const orc_scene *s, uint64_t n, const double *o, const double *d,
                     int use_bvh, int64_t *prim, double *t);

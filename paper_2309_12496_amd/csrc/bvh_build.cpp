@@ -1,0 +1,340 @@
+// Binned-SAH BVH builder: a binary tree built in FP64 over triangle centroids,
+// collapsed into 4-wide nodes whose children are the (up to) four largest
+// descendants, stored depth-first with FP32 boxes rounded outward.
+#include "bvh_build.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace rich {
+
+namespace {
+
+constexpr int kBins = 32;
+constexpr uint32_t kLeafSize = 4;
+
+struct BNode {
+    BuildBox box;
+    int left = -1, right = -1;
+    uint32_t first = 0, count = 0;
+};
+
+BuildBox empty_box() {
+    BuildBox b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::numeric_limits<double>::infinity();
+        b.hi[a] = -std::numeric_limits<double>::infinity();
+    }
+    return b;
+}
+
+void grow(BuildBox &b, const double *p) {
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::min(b.lo[a], p[a]);
+        b.hi[a] = std::max(b.hi[a], p[a]);
+    }
+}
+
+void grow(BuildBox &b, const BuildBox &o) {
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::min(b.lo[a], o.lo[a]);
+        b.hi[a] = std::max(b.hi[a], o.hi[a]);
+    }
+}
+
+double area(const BuildBox &b) {
+    double dx = b.hi[0] - b.lo[0], dy = b.hi[1] - b.lo[1], dz = b.hi[2] - b.lo[2];
+    if (dx < 0 || dy < 0 || dz < 0) return 0.0;
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+}
+
+struct Builder {
+    std::vector<BuildTri> &tris;
+    std::vector<BuildBox> tbox;
+    std::vector<double> cen;  // [n][3]
+    std::vector<uint32_t> idx;
+    std::vector<BNode> bn;
+
+    explicit Builder(std::vector<BuildTri> &t) : tris(t) {
+        size_t n = t.size();
+        tbox.resize(n);
+        cen.resize(3 * n);
+        idx.resize(n);
+        for (size_t i = 0; i < n; ++i) {
+            BuildBox b = empty_box();
+            for (int m = 0; m < 3; ++m) grow(b, t[i].v[m]);
+            tbox[i] = b;
+            for (int a = 0; a < 3; ++a) cen[3 * i + a] = 0.5 * (b.lo[a] + b.hi[a]);
+            idx[i] = (uint32_t)i;
+        }
+    }
+
+    int build(uint32_t first, uint32_t count) {
+        int me = (int)bn.size();
+        bn.emplace_back();
+        BuildBox box = empty_box(), cb = empty_box();
+        for (uint32_t q = first; q < first + count; ++q) {
+            grow(box, tbox[idx[q]]);
+            grow(cb, &cen[3 * idx[q]]);
+        }
+        bn[me].box = box;
+        bn[me].first = first;
+        bn[me].count = count;
+        if (count <= kLeafSize) return me;
+
+        // binned SAH over the centroid bounds
+        double best_cost = std::numeric_limits<double>::infinity();
+        int best_axis = -1, best_split = -1;
+        for (int a = 0; a < 3; ++a) {
+            double ext = cb.hi[a] - cb.lo[a];
+            if (!(ext > 0)) continue;
+            double scale = kBins / ext;
+            BuildBox bb[kBins];
+            uint32_t bc[kBins] = {};
+            for (int k = 0; k < kBins; ++k) bb[k] = empty_box();
+            for (uint32_t q = first; q < first + count; ++q) {
+                int k = std::min(kBins - 1, (int)((cen[3 * idx[q] + a] - cb.lo[a]) * scale));
+                ++bc[k];
+                grow(bb[k], tbox[idx[q]]);
+            }
+            double right_area[kBins];
+            uint32_t right_cnt[kBins];
+            BuildBox acc = empty_box();
+            uint32_t cnt = 0;
+            for (int k = kBins - 1; k > 0; --k) {
+                grow(acc, bb[k]);
+                cnt += bc[k];
+                right_area[k] = area(acc);
+                right_cnt[k] = cnt;
+            }
+            acc = empty_box();
+            cnt = 0;
+            for (int k = 0; k < kBins - 1; ++k) {
+                grow(acc, bb[k]);
+                cnt += bc[k];
+                if (cnt == 0 || right_cnt[k + 1] == 0) continue;
+                double cost = area(acc) * cnt + right_area[k + 1] * right_cnt[k + 1];
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_split = k + 1;
+                }
+            }
+        }
+        uint32_t mid;
+        if (best_axis >= 0) {
+            double ext = cb.hi[best_axis] - cb.lo[best_axis];
+            double scale = kBins / ext;
+            auto it = std::partition(idx.begin() + first, idx.begin() + first + count, [&](uint32_t i) {
+                int k = std::min(kBins - 1, (int)((cen[3 * i + best_axis] - cb.lo[best_axis]) * scale));
+                return k < best_split;
+            });
+            mid = (uint32_t)(it - idx.begin());
+        } else {
+            mid = first + count / 2;  // all centroids coincide: split the index range
+        }
+        if (mid == first || mid == first + count) mid = first + count / 2;
+        int l = build(first, mid - first);
+        int r = build(mid, first + count - mid);
+        bn[me].left = l;
+        bn[me].right = r;
+        return me;
+    }
+};
+
+void set_child_box(Node4 &nd, int k, const BuildBox &b) {
+    nd.lox[k] = lower_f32(b.lo[0]);
+    nd.loy[k] = lower_f32(b.lo[1]);
+    nd.loz[k] = lower_f32(b.lo[2]);
+    nd.hix[k] = upper_f32(b.hi[0]);
+    nd.hiy[k] = upper_f32(b.hi[1]);
+    nd.hiz[k] = upper_f32(b.hi[2]);
+}
+
+void clear_node(Node4 &nd) {
+    for (int k = 0; k < 4; ++k) {
+        nd.lox[k] = nd.loy[k] = nd.loz[k] = std::numeric_limits<float>::infinity();
+        nd.hix[k] = nd.hiy[k] = nd.hiz[k] = -std::numeric_limits<float>::infinity();
+        nd.child[k] = kEmpty;
+        nd.pad[k] = 0;
+    }
+}
+
+// Pick up to four descendants of a binary node: repeatedly open the largest internal one.
+std::vector<int> gather4(const std::vector<BNode> &bn, int root) {
+    std::vector<int> kids;
+    if (bn[root].left < 0) {
+        kids.push_back(root);
+        return kids;
+    }
+    kids = {bn[root].left, bn[root].right};
+    while (kids.size() < 4) {
+        int pick = -1;
+        double best = -1;
+        for (size_t k = 0; k < kids.size(); ++k) {
+            const BNode &c = bn[kids[k]];
+            if (c.left >= 0 && area(c.box) > best) {
+                best = area(c.box);
+                pick = (int)k;
+            }
+        }
+        if (pick < 0) break;
+        int c = kids[pick];
+        kids.erase(kids.begin() + pick);
+        kids.push_back(bn[c].left);
+        kids.push_back(bn[c].right);
+    }
+    return kids;
+}
+
+struct Emitter {
+    const std::vector<BNode> &bn;
+    const std::vector<uint32_t> &idx;
+    const std::vector<BuildTri> &tris;
+    std::vector<Node4> &nodes;
+    std::vector<Tri> &out;
+    int max_depth = 0;
+
+    uint32_t leaf_ref(const BNode &b) {
+        uint32_t first = (uint32_t)out.size();
+        for (uint32_t q = b.first; q < b.first + b.count; ++q) {
+            const BuildTri &t = tris[idx[q]];
+            Tri r;
+            for (int a = 0; a < 3; ++a) {
+                r.v0[a] = (float)t.v[0][a];
+                r.v1[a] = (float)t.v[1][a];
+                r.v2[a] = (float)t.v[2][a];
+                r.n[a] = (float)t.n[a];
+            }
+            r.index = t.index;
+            r.material = t.material;
+            r.pad0 = r.pad1 = 0;
+            out.push_back(r);
+        }
+        return make_leaf(first, b.count);
+    }
+
+    uint32_t emit(int root, int depth) {
+        max_depth = std::max(max_depth, depth);
+        uint32_t me = (uint32_t)nodes.size();
+        nodes.emplace_back();
+        clear_node(nodes[me]);
+        std::vector<int> kids = gather4(bn, root);
+        for (size_t k = 0; k < kids.size(); ++k) {
+            const BNode &c = bn[kids[k]];
+            uint32_t ref = (c.left < 0) ? leaf_ref(c) : emit(kids[k], depth + 1);
+            Node4 &nd = nodes[me];
+            set_child_box(nd, (int)k, c.box);
+            nd.child[k] = ref;
+        }
+        return me;
+    }
+};
+
+}  // namespace
+
+float lower_f32(double x) {
+    double pad = 1e-3 + 1e-6 * std::fabs(x);
+    float f = (float)(x - pad);
+    while ((double)f > x - pad) f = std::nextafter(f, -std::numeric_limits<float>::infinity());
+    return f;
+}
+
+float upper_f32(double x) {
+    double pad = 1e-3 + 1e-6 * std::fabs(x);
+    float f = (float)(x + pad);
+    while ((double)f < x + pad) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+    return f;
+}
+
+uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes, std::vector<Tri> &out, int *depth,
+                         BuildBox *bounds) {
+    Builder b(tris);
+    b.bn.reserve(2 * tris.size() / kLeafSize + 2);
+    b.build(0, (uint32_t)tris.size());
+    if (bounds) *bounds = b.bn[0].box;
+    Emitter e{b.bn, b.idx, tris, nodes, out};
+    uint32_t root = e.emit(0, 1);
+    if (depth) *depth = e.max_depth;
+    return root;
+}
+
+uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &nodes, int *depth) {
+    // binary SAH over instance boxes, treated as degenerate triangles through their corners
+    std::vector<BuildTri> pseudo(boxes.size());
+    for (size_t i = 0; i < boxes.size(); ++i) {
+        for (int a = 0; a < 3; ++a) {
+            pseudo[i].v[0][a] = boxes[i].lo[a];
+            pseudo[i].v[1][a] = boxes[i].hi[a];
+            pseudo[i].v[2][a] = boxes[i].lo[a];
+            pseudo[i].n[a] = 0;
+        }
+        pseudo[i].index = (uint32_t)i;
+        pseudo[i].material = 0;
+    }
+    // one instance per leaf: build with leaf size 1 by splitting until single
+    struct TopBuilder {
+        std::vector<BuildTri> &t;
+        std::vector<uint32_t> idx;
+        std::vector<BNode> bn;
+        int build(uint32_t first, uint32_t count, const std::vector<BuildBox> &bx) {
+            int me = (int)bn.size();
+            bn.emplace_back();
+            BuildBox box = empty_box();
+            for (uint32_t q = first; q < first + count; ++q) grow(box, bx[idx[q]]);
+            bn[me].box = box;
+            bn[me].first = first;
+            bn[me].count = count;
+            if (count == 1) return me;
+            int axis = 0;
+            double ext[3];
+            for (int a = 0; a < 3; ++a) ext[a] = box.hi[a] - box.lo[a];
+            if (ext[1] > ext[axis]) axis = 1;
+            if (ext[2] > ext[axis]) axis = 2;
+            std::sort(idx.begin() + first, idx.begin() + first + count, [&](uint32_t a, uint32_t b) {
+                double ca = bx[a].lo[axis] + bx[a].hi[axis], cb = bx[b].lo[axis] + bx[b].hi[axis];
+                return ca < cb || (ca == cb && a < b);
+            });
+            uint32_t mid = first + count / 2;
+            int l = build(first, mid - first, bx);
+            int r = build(mid, first + count - mid, bx);
+            bn[me].left = l;
+            bn[me].right = r;
+            return me;
+        }
+    } tb{pseudo, {}, {}};
+    tb.idx.resize(boxes.size());
+    for (size_t i = 0; i < boxes.size(); ++i) tb.idx[i] = (uint32_t)i;
+    tb.build(0, (uint32_t)boxes.size(), boxes);
+
+    int maxd = 0;
+    std::vector<Node4> &nd = nodes;
+    struct TopEmit {
+        const std::vector<BNode> &bn;
+        const std::vector<uint32_t> &idx;
+        std::vector<Node4> &nodes;
+        int &maxd;
+        uint32_t emit(int root, int depth) {
+            maxd = std::max(maxd, depth);
+            uint32_t me = (uint32_t)nodes.size();
+            nodes.emplace_back();
+            clear_node(nodes[me]);
+            std::vector<int> kids;
+            if (bn[root].left < 0) kids.push_back(root);
+            else kids = gather4(bn, root);
+            for (size_t k = 0; k < kids.size(); ++k) {
+                const BNode &c = bn[kids[k]];
+                uint32_t ref = (c.left < 0) ? make_inst(idx[c.first]) : emit(kids[k], depth + 1);
+                set_child_box(nodes[me], (int)k, c.box);
+                nodes[me].child[k] = ref;
+            }
+            return me;
+        }
+    } te{tb.bn, tb.idx, nd, maxd};
+    uint32_t root = te.emit(0, 1);
+    if (depth) *depth = maxd;
+    return root;
+}
+
+}  // namespace rich

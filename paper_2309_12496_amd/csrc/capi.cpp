@@ -1,0 +1,481 @@
+// C ABI of librich: argument checks, source set-up, launches, graph capture,
+// autotuning and status.  No exception crosses these functions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/rich.h"
+#include "kernels.h"
+#include "scene.h"
+
+namespace rich {
+const char *last_error();
+}
+
+using namespace rich;
+
+namespace {
+
+// Makes the scene's device current for the lifetime of a call.
+struct DeviceGuard {
+    int prev = 0;
+    explicit DeviceGuard(int dev) {
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+#define RICH_HIP(call)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return set_error(RICH_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+rich_status check_spectrum(double n, double lmin, double lmax) {
+    if (!(n > 0) || !std::isfinite(n)) return set_error(RICH_EINVAL, "n_radiator must be finite and > 0");
+    if (!(lmin > 0) || !(lmax > lmin) || !std::isfinite(lmax))
+        return set_error(RICH_EINVAL, "need 0 < lambda_min < lambda_max");
+    return RICH_OK;
+}
+
+// Host FP64 set-up of a single track source: unit direction, its orthonormal
+// basis (Duff et al., JCGT 2017), the Cherenkov cone cos = 1/(n beta) and the
+// wavelength inverse-CDF constants, rounded once to FP32.
+rich_status make_track_source(const rich_source *src, DevSource &ds) {
+    std::memset(&ds, 0, sizeof ds);
+    if (src->kind == RICH_SRC_EXPLICIT) {
+        if (!src->dev_o || !src->dev_d || !src->dev_lambda)
+            return set_error(RICH_EINVAL, "explicit source needs dev_o, dev_d and dev_lambda");
+        ds.kind = 2;
+        ds.ex_o = src->dev_o;
+        ds.ex_d = src->dev_d;
+        ds.ex_l = src->dev_lambda;
+        return RICH_OK;
+    }
+    if (src->kind != RICH_SRC_TRACK) return set_error(RICH_EINVAL, "unknown source kind %d", src->kind);
+    rich_status st = check_spectrum(src->n_radiator, src->lambda_min, src->lambda_max);
+    if (st) return st;
+    const double *o = src->origin, *t = src->direction;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(o[a]) || !std::isfinite(t[a])) return set_error(RICH_EINVAL, "track origin/direction not finite");
+    if (!std::isfinite(src->length) || src->length < 0) return set_error(RICH_EINVAL, "track length must be >= 0");
+    double nb = src->n_radiator * src->beta;
+    if (!(nb > 1.0) || !std::isfinite(nb)) return set_error(RICH_EINVAL, "n*beta = %g: no Cherenkov light", nb);
+    double len = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    if (!(len > 0)) return set_error(RICH_EINVAL, "track direction is zero");
+    double T[3] = {t[0] / len, t[1] / len, t[2] / len};
+    double sgn = std::copysign(1.0, T[2]);
+    double a = -1.0 / (sgn + T[2]);
+    double b = T[0] * T[1] * a;
+    double E1[3] = {1.0 + sgn * T[0] * T[0] * a, sgn * b, -sgn * T[0]};
+    double E2[3] = {b, sgn + T[1] * T[1] * a, -T[1]};
+    double c = 1.0 / nb;
+    ds.kind = 0;
+    for (int q = 0; q < 3; ++q) {
+        ds.P0[q] = (float)o[q];
+        ds.T[q] = (float)T[q];
+        ds.E1[q] = (float)E1[q];
+        ds.E2[q] = (float)E2[q];
+    }
+    ds.length = (float)src->length;
+    ds.cos_t = (float)c;
+    ds.sin_t = (float)std::sqrt((1.0 - c) * (1.0 + c));
+    ds.inv_lmin = (float)(1.0 / src->lambda_min);
+    ds.inv_span = (float)(1.0 / src->lambda_min - 1.0 / src->lambda_max);
+    return RICH_OK;
+}
+
+rich_status make_batch_source(const rich_batch *b, DevSource &ds) {
+    std::memset(&ds, 0, sizeof ds);
+    if (!b->dev_tracks || !b->dev_offsets || b->n_tracks < 1)
+        return set_error(RICH_EINVAL, "batch needs tracks, offsets and n_tracks >= 1");
+    rich_status st = check_spectrum(b->n_radiator, b->lambda_min, b->lambda_max);
+    if (st) return st;
+    ds.kind = 1;
+    ds.tracks = reinterpret_cast<const float *>(b->dev_tracks);
+    ds.offsets = b->dev_offsets;
+    ds.n_tracks = b->n_tracks;
+    ds.n_radiator = b->n_radiator;
+    ds.inv_lmin = (float)(1.0 / b->lambda_min);
+    ds.inv_span = (float)(1.0 / b->lambda_min - 1.0 / b->lambda_max);
+    return RICH_OK;
+}
+
+DevOutputs make_outputs(const rich_outputs *o) {
+    DevOutputs d;
+    std::memset(&d, 0, sizeof d);
+    if (!o) return d;
+    d.fate = o->fate;
+    d.pixel = o->pixel;
+    d.hit_xyz = o->hit_xyz;
+    d.hit_uv = o->hit_uv;
+    d.histogram = o->histogram;
+    d.fate_counts = o->fate_counts;
+    d.hit_list = o->hit_list;
+    d.hit_count = o->hit_count;
+    d.hit_capacity = o->hit_list_capacity;
+    return d;
+}
+
+rich_status check_outputs(const rich_outputs *o) {
+    if (!o) return RICH_OK;
+    if (o->hit_list && !o->hit_count) return set_error(RICH_EINVAL, "hit_list needs hit_count");
+    return RICH_OK;
+}
+
+// ------------------------------------------------------------- autotune cache
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    return std::string(p.gcnArchName);
+}
+
+std::string tune_key(const rich_scene *s, uint64_t n) {
+    int tb = 0;
+    for (int64_t x = s->stats.n_triangles; x > 1; x >>= 1) ++tb;
+    int nb = 0;
+    for (uint64_t x = n; x > 1; x >>= 1) ++nb;
+    std::ostringstream k;
+    k << arch_name(s->device) << "/cu" << s->n_cu << "/tri2^" << tb << "/caps" << s->dev.n_caps << "/n2^" << nb;
+    return k.str();
+}
+
+bool load_tuning_file(const std::string &key, rich_tuning *t) {
+    const char *path = std::getenv("RICH_TUNE_CACHE");
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // one entry per line: "key": [block, chunk, blocks_per_cu],
+        size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+        if (q0 == std::string::npos || q1 == std::string::npos) continue;
+        if (line.substr(q0 + 1, q1 - q0 - 1) != key) continue;
+        int b, c, p;
+        if (std::sscanf(line.c_str() + q1 + 1, " : [%d , %d , %d]", &b, &c, &p) == 3) {
+            t->block = b;
+            t->chunk = c;
+            t->blocks_per_cu = p;
+            return true;
+        }
+    }
+    return false;
+}
+
+void store_tuning_file(const std::string &key, const rich_tuning &t) {
+    const char *path = std::getenv("RICH_TUNE_CACHE");
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+            if (q0 == std::string::npos || q1 == std::string::npos) continue;
+            if (line.substr(q0 + 1, q1 - q0 - 1) == key) continue;
+            std::string e = line;
+            while (!e.empty() && (e.back() == ',' || e.back() == ' ')) e.pop_back();
+            keep.push_back(e);
+        }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "  \"%s\": [%d, %d, %d]", key.c_str(), t.block, t.chunk, t.blocks_per_cu);
+    keep.push_back(buf);
+    std::ofstream f(path);
+    f << "{\n";
+    for (size_t i = 0; i < keep.size(); ++i) f << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+rich_status valid_tuning(const rich_tuning *t) {
+    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
+        return set_error(RICH_EINVAL, "tuning.block must be 64, 128, 256 or 512");
+    if (t->chunk < 64 || t->chunk % 64 != 0 || t->chunk > 65536)
+        return set_error(RICH_EINVAL, "tuning.chunk must be a multiple of 64 in 64..65536");
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return set_error(RICH_EINVAL, "tuning.blocks_per_cu in 1..64");
+    return RICH_OK;
+}
+
+int grid_of(const rich_scene *s, const rich_tuning &t) { return std::max(1, s->n_cu * t.blocks_per_cu); }
+
+rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64_t seed, rich_tuning *best_out) {
+    uint64_t n_t = std::min<uint64_t>(n, 4000000ull);
+    if (n_t == 0) {
+        *best_out = rich_tuning{256, 256, 4, 0};
+        return RICH_OK;
+    }
+    // scratch outputs so the caller's accumulating outputs stay untouched
+    uint8_t *fate = nullptr;
+    int32_t *pixel = nullptr;
+    float *xyz = nullptr, *uv = nullptr;
+    uint32_t *hist = nullptr;
+    unsigned long long *counts = nullptr, *counter = nullptr;
+    size_t nh = (size_t)s->nx * s->ny;
+    hipError_t e = hipSuccess;
+    e = e == hipSuccess ? hipMalloc(&fate, n_t) : e;
+    e = e == hipSuccess ? hipMalloc(&pixel, 4 * n_t) : e;
+    e = e == hipSuccess ? hipMalloc(&xyz, 12 * n_t) : e;
+    e = e == hipSuccess ? hipMalloc(&uv, 8 * n_t) : e;
+    e = e == hipSuccess ? hipMalloc(&hist, 4 * nh) : e;
+    e = e == hipSuccess ? hipMalloc(&counts, 8 * RICH_N_FATES) : e;
+    e = e == hipSuccess ? hipMalloc(&counter, 8) : e;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = e == hipSuccess ? hipEventCreate(&a) : e;
+    e = e == hipSuccess ? hipEventCreate(&b) : e;
+    rich_status st = RICH_OK;
+    if (e != hipSuccess) {
+        st = set_error(RICH_ENOMEM, "autotune scratch allocation failed: %s", hipGetErrorString(e));
+    } else {
+        DevOutputs out;
+        std::memset(&out, 0, sizeof out);
+        out.fate = fate;
+        out.pixel = pixel;
+        out.hit_xyz = xyz;
+        out.hit_uv = uv;
+        out.histogram = hist;
+        out.fate_counts = counts;
+        float best = INFINITY;
+        rich_tuning bt{256, 256, 4, 0};
+        const int blocks[] = {64, 128, 256, 512};
+        const int chunks[] = {64, 128, 256, 512, 1024};
+        for (int blk : blocks) {
+            int max_bpc = (int)std::min<long>(16, (160L * 1024) / ((long)blk * kStackDepth * 4));
+            for (int bpc = 1; bpc <= max_bpc; bpc *= 2) {
+                for (int ch : chunks) {
+                    rich_tuning t{blk, ch, bpc, 0};
+                    float tmin = INFINITY;
+                    for (int rep = 0; rep < 3 && st == RICH_OK; ++rep) {
+                        hipError_t r1 = launch_fill_u64(counter, 1, nullptr);
+                        (void)hipEventRecord(a, nullptr);
+                        hipError_t r2 = launch_batch(s->dev, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), nullptr);
+                        (void)hipEventRecord(b, nullptr);
+                        if (r1 != hipSuccess || r2 != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+                            st = set_error(RICH_EDEVICE, "autotune launch failed");
+                            break;
+                        }
+                        float ms = 0;
+                        (void)hipEventElapsedTime(&ms, a, b);
+                        if (rep > 0) tmin = std::min(tmin, ms);
+                    }
+                    if (st != RICH_OK) break;
+                    if (tmin < best) {
+                        best = tmin;
+                        bt = t;
+                    }
+                }
+            }
+        }
+        *best_out = bt;
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    void *ptrs[] = {fate, pixel, xyz, uv, hist, counts, counter};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rich_last_error(void) { return last_error(); }
+
+const char *rich_version(void) { return "richprop 0.1 (gfx950)"; }
+
+rich_status rich_build_scene(const rich_scene_desc *desc, int device, rich_scene **out) {
+    if (!out) return set_error(RICH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!desc) return set_error(RICH_EINVAL, "desc is NULL");
+    try {
+        return build_scene(desc, device, out);
+    } catch (const std::bad_alloc &) {
+        return set_error(RICH_ENOMEM, "host allocation failed while building the scene");
+    } catch (...) {
+        return set_error(RICH_EINVAL, "scene build failed");
+    }
+}
+
+rich_status rich_destroy_scene(rich_scene *s) {
+    if (!s) return set_error(RICH_EINVAL, "scene is NULL");
+    free_scene(s);
+    return RICH_OK;
+}
+
+rich_status rich_scene_info(const rich_scene *s, rich_scene_stats *out) {
+    if (!s || !out) return set_error(RICH_EINVAL, "scene and out must not be NULL");
+    *out = s->stats;
+    return RICH_OK;
+}
+
+rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipStream_t stream) {
+    if (!s) return set_error(RICH_EINVAL, "scene is NULL");
+    if (s->n_segments == 0) return set_error(RICH_ESTATE, "scene has no parametrised segments");
+    if (!dev_params) return set_error(RICH_EINVAL, "dev_params is NULL");
+    DeviceGuard g(s->device);
+    RICH_HIP(hipMemcpyAsync(s->d_params, dev_params, sizeof(float) * 6 * s->n_segments, hipMemcpyDeviceToDevice,
+                            stream));
+    PrepareArgs pa{s->d_segs, s->d_caps_static, s->d_params, s->d_caps, s->dev.n_caps, s->d_inst, s->dev.n_inst,
+                   s->d_nodes, s->n_top};
+    RICH_HIP(launch_prepare(pa, stream));
+    return RICH_OK;
+}
+
+rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,
+                           uint64_t first_photon_id, const rich_outputs *out, hipStream_t stream) {
+    if (!s || !src) return set_error(RICH_EINVAL, "scene and source must not be NULL");
+    if (first_photon_id + n_photons < first_photon_id) return set_error(RICH_ERANGE, "photon id range wraps 2^64");
+    if (n_photons > (1ull << 40)) return set_error(RICH_ERANGE, "n_photons too large for one call");
+    rich_status st = check_outputs(out);
+    if (st) return st;
+    DevSource ds;
+    if ((st = make_track_source(src, ds))) return st;
+    if (n_photons == 0) return RICH_OK;
+    DeviceGuard g(s->device);
+    RICH_HIP(launch_forward(s->dev, ds, make_outputs(out), n_photons, first_photon_id, seed, stream));
+    return RICH_OK;
+}
+
+rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
+                          rich_tuning *out) {
+    if (!s || !batch || !out) return set_error(RICH_EINVAL, "scene, batch and out must not be NULL");
+    DevSource ds;
+    rich_status st = make_batch_source(batch, ds);
+    if (st) return st;
+    DeviceGuard g(s->device);
+    try {
+        return run_autotune(s, ds, n_photons, seed, out);
+    } catch (...) {
+        return set_error(RICH_ENOMEM, "autotune failed");
+    }
+}
+
+rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
+                                 const rich_outputs *out, const rich_tuning *tune, hipStream_t stream) {
+    if (!s || !batch) return set_error(RICH_EINVAL, "scene and batch must not be NULL");
+    if (n_photons > (1ull << 40)) return set_error(RICH_ERANGE, "n_photons too large for one call");
+    rich_status st = check_outputs(out);
+    if (st) return st;
+    DevSource ds;
+    if ((st = make_batch_source(batch, ds))) return st;
+    if (n_photons == 0) return RICH_OK;
+    DeviceGuard g(s->device);
+    try {
+        rich_tuning t;
+        if (tune) {
+            if ((st = valid_tuning(tune))) return st;
+            t = *tune;
+        } else {
+            std::string key = tune_key(s, n_photons);
+            auto it = s->tuned.find(key);
+            if (it != s->tuned.end()) {
+                t = it->second;
+            } else if (!load_tuning_file(key, &t) || valid_tuning(&t) != RICH_OK) {
+                RICH_HIP(hipStreamSynchronize(stream));
+                if ((st = run_autotune(s, ds, n_photons, seed, &t))) return st;
+                store_tuning_file(key, t);
+                s->tuned[key] = t;
+            } else {
+                s->tuned[key] = t;
+            }
+        }
+        DevOutputs dout = make_outputs(out);
+        char key[512];
+        std::snprintf(key, sizeof key, "%p/%p/%d/%llu/%llu/%p/%p/%p/%p/%p/%p/%p/%p/%llu/%d/%d/%d",
+                      (const void *)batch->dev_tracks, (const void *)batch->dev_offsets, batch->n_tracks,
+                      (unsigned long long)n_photons, (unsigned long long)seed, (void *)dout.fate, (void *)dout.pixel,
+                      (void *)dout.hit_xyz, (void *)dout.hit_uv, (void *)dout.histogram, (void *)dout.fate_counts,
+                      dout.hit_list, (void *)dout.hit_count, (unsigned long long)dout.hit_capacity, t.block, t.chunk,
+                      t.blocks_per_cu);
+        std::string k2 = std::string(key) + "/" + std::to_string(batch->n_radiator) + "/" +
+                         std::to_string(batch->lambda_min) + "/" + std::to_string(batch->lambda_max);
+        if (!s->graph_exec || s->graph_key != k2) {
+            if (s->graph_exec) {
+                (void)hipGraphExecDestroy(s->graph_exec);
+                s->graph_exec = nullptr;
+            }
+            if (s->graph) {
+                (void)hipGraphDestroy(s->graph);
+                s->graph = nullptr;
+            }
+            if (!s->capture_stream) RICH_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+            RICH_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = launch_fill_u64(s->d_counter, 1, s->capture_stream);
+            hipError_t e2 = launch_batch(s->dev, ds, dout, n_photons, seed, s->d_counter, t.block, t.chunk,
+                                         grid_of(s, t), s->capture_stream);
+            hipGraph_t gr = nullptr;
+            hipError_t e3 = hipStreamEndCapture(s->capture_stream, &gr);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return set_error(RICH_EDEVICE, "graph capture failed");
+            }
+            s->graph = gr;
+            RICH_HIP(hipGraphInstantiate(&s->graph_exec, s->graph, nullptr, nullptr, 0));
+            s->graph_key = k2;
+        }
+        RICH_HIP(hipGraphLaunch(s->graph_exec, stream));
+        return RICH_OK;
+    } catch (...) {
+        return set_error(RICH_ENOMEM, "batch launch failed");
+    }
+}
+
+rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
+                                   uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
+                                   const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
+                                   float *dev_grad_params, float *dev_loss, hipStream_t stream) {
+    if (!s) return set_error(RICH_EINVAL, "scene is NULL");
+    if ((src == nullptr) == (batch == nullptr)) return set_error(RICH_EINVAL, "give exactly one of src and batch");
+    if ((dev_grad_uv == nullptr) == (dev_targets == nullptr))
+        return set_error(RICH_EINVAL, "give exactly one of dev_grad_uv and dev_targets");
+    if (!dev_grad_params) return set_error(RICH_EINVAL, "dev_grad_params is NULL");
+    if (s->n_segments == 0) return set_error(RICH_ESTATE, "scene has no parametrised segments");
+    if (first_photon_id + n_photons < first_photon_id) return set_error(RICH_ERANGE, "photon id range wraps 2^64");
+    if (n_photons > (1ull << 40)) return set_error(RICH_ERANGE, "n_photons too large for one call");
+    DevSource ds;
+    rich_status st = src ? make_track_source(src, ds) : make_batch_source(batch, ds);
+    if (st) return st;
+    if (batch && first_photon_id != 0) return set_error(RICH_EINVAL, "batch photons start at id 0");
+    DeviceGuard g(s->device);
+    int n_par = 6 * s->n_segments;
+    int block = adjoint_block_size();
+    uint64_t per_block = (uint64_t)block * 8;
+    uint64_t nb = (n_photons + per_block - 1) / per_block;
+    int n_blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(nb, (uint64_t)s->n_cu * 16));
+    size_t need = (size_t)n_blocks * (n_par + 2);
+    if (need > s->partials_floats) {
+        if (s->d_partials) (void)hipFree(s->d_partials);
+        s->d_partials = nullptr;
+        s->partials_floats = 0;
+        if (hipMalloc(&s->d_partials, need * sizeof(float)) != hipSuccess)
+            return set_error(RICH_ENOMEM, "adjoint partials allocation failed");
+        s->partials_floats = need;
+    }
+    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, s->d_partials, dev_grad_params, dev_loss, n_par};
+    RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, n_blocks, stream));
+    return RICH_OK;
+}
+
+rich_status rich_get_status(rich_scene *s, hipStream_t stream, uint32_t *flags) {
+    if (!s) return set_error(RICH_EINVAL, "scene is NULL");
+    DeviceGuard g(s->device);
+    RICH_HIP(hipStreamSynchronize(stream));
+    unsigned int f = 0;
+    RICH_HIP(hipMemcpy(&f, s->d_status, sizeof f, hipMemcpyDeviceToHost));
+    unsigned int zero = 0;
+    RICH_HIP(hipMemcpy(s->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (flags) *flags = f;
+    if (f) return set_error(RICH_EOVERFLOW, "device flags 0x%x raised", f);
+    return RICH_OK;
+}
+
+}  // extern "C"

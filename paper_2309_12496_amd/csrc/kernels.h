@@ -1,0 +1,42 @@
+// Host-side launchers of the librich kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rich_dev.h"
+
+namespace rich {
+
+struct PrepareArgs {
+    const SegDev *segs;
+    const CapStatic *caps_static;
+    const float *params;        // [n_seg][6]
+    CapDev *caps;
+    int32_t n_caps;
+    Instance *inst;
+    int32_t n_inst;
+    Node4 *nodes;               // top-level nodes occupy [0, n_top)
+    int32_t n_top;
+};
+
+hipError_t launch_prepare(const PrepareArgs &a, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st);
+hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n,
+                          uint64_t first, uint64_t seed, hipStream_t st);
+hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
+                        unsigned long long *counter, int block, int chunk, int grid, hipStream_t st);
+
+struct AdjointArgs {
+    const float *grad_uv;       // [N][2] or null
+    const float *targets;       // [N][2] or null
+    const uint8_t *mask;        // [N] or null (all)
+    float *partials;            // [n_blocks][n_par + 2]
+    float *grad;                // [n_seg][6]
+    float *loss;                // [1] or null
+    int32_t n_par;
+};
+hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const AdjointArgs &a, uint64_t n, uint64_t first,
+                          uint64_t seed, int n_blocks, hipStream_t st);
+int adjoint_block_size();
+
+}  // namespace rich

@@ -1,0 +1,314 @@
+// librich kernels for gfx950: parameter refresh, forward propagation (one
+// photon per lane), the persistent batch kernel, and small helpers.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "trace.h"
+
+namespace rich {
+
+// ---------------------------------------------------------------- parameters (FP64)
+
+namespace {
+
+struct D3 {
+    double x, y, z;
+};
+__device__ inline D3 dload(const double *p) { return D3{p[0], p[1], p[2]}; }
+__device__ inline D3 dadd(D3 a, D3 b) { return D3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline D3 dsub(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 dmul(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
+__device__ inline double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline D3 dcross(D3 a, D3 b) {
+    return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// rotation of v about unit axis k by angle th (Rodrigues)
+__device__ inline D3 drot(D3 k, double th, D3 v) {
+    double c = cos(th), s = sin(th);
+    return dadd(dadd(dmul(v, c), dmul(dcross(k, v), s)), dmul(k, ddot(k, v) * (1.0 - c)));
+}
+__device__ inline void store3(float *p, D3 v) {
+    p[0] = (float)v.x;
+    p[1] = (float)v.y;
+    p[2] = (float)v.z;
+}
+
+}  // namespace
+
+// One thread per cap and per instance; thread 0 then refits the top-level boxes.
+__global__ void prepare_kernel(PrepareArgs a) {
+    int tid = threadIdx.x;
+    for (int i = tid; i < a.n_caps; i += blockDim.x) {
+        const CapStatic &cs = a.caps_static[i];
+        const SegDev &sg = a.segs[cs.segment];
+        const float *p = a.params + 6 * cs.segment;
+        double tx = p[0], ty = p[1], R = p[2];
+        D3 e1 = dload(sg.e1), e2 = dload(sg.e2), u0 = dload(sg.u0);
+        D3 r1 = drot(e1, tx, u0);
+        D3 ax = drot(e2, ty, r1);
+        D3 C = dadd(dadd(dload(sg.pivot), D3{p[3], p[4], p[5]}), dmul(ax, R));
+        CapDev &cd = a.caps[i];
+        store3(cd.C, C);
+        cd.R = (float)R;
+        store3(cd.axis, ax);
+        cd.segment = cs.segment;
+        store3(cd.O, dload(cs.O));
+        cd.material = cs.material;
+        store3(cd.A, dload(cs.A));
+        store3(cd.B, dload(cs.B));
+        cd.a_lo = (float)cs.bounds[0];
+        cd.a_hi = (float)cs.bounds[1];
+        cd.b_lo = (float)cs.bounds[2];
+        cd.b_hi = (float)cs.bounds[3];
+        store3(cd.dCdtx, dmul(drot(e2, ty, dcross(e1, r1)), R));
+        store3(cd.dCdty, dmul(dcross(e2, ax), R));
+        // box of the cap: the cell prism over the sphere heights reached inside the cell
+        D3 O = dload(cs.O), A = dload(cs.A), B = dload(cs.B);
+        D3 W = dcross(A, B);
+        D3 CO = dsub(C, O);
+        double ca = ddot(CO, A), cb = ddot(CO, B), cw = ddot(CO, W);
+        double sgn = ddot(ax, W) > 0 ? -1.0 : 1.0;   // pivot side of the centre along W
+        double qa = fmin(fmax(ca, cs.bounds[0]), cs.bounds[1]) - ca;
+        double qb = fmin(fmax(cb, cs.bounds[2]), cs.bounds[3]) - cb;
+        double rmin2 = qa * qa + qb * qb;
+        double fa = fmax(fabs(cs.bounds[0] - ca), fabs(cs.bounds[1] - ca));
+        double fb = fmax(fabs(cs.bounds[2] - cb), fabs(cs.bounds[3] - cb));
+        double rmax2 = fa * fa + fb * fb;
+        double h0 = cw + sgn * sqrt(fmax(0.0, R * R - rmax2));
+        double h1 = cw + sgn * sqrt(fmax(0.0, R * R - rmin2));
+        double hlo = fmin(h0, h1), hhi = fmax(h0, h1);
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int c = 0; c < 8; ++c) {
+            double aa = cs.bounds[(c & 1) ? 1 : 0], bb = cs.bounds[(c & 2) ? 3 : 2], hh = (c & 4) ? hhi : hlo;
+            D3 P = dadd(dadd(dadd(O, dmul(A, aa)), dmul(B, bb)), dmul(W, hh));
+            double q[3] = {P.x, P.y, P.z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], q[k]);
+                hi[k] = fmax(hi[k], q[k]);
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double pad = 1e-2 + 1e-6 * fmax(fabs(lo[k]), fabs(hi[k]));
+            cd.lo[k] = (float)(lo[k] - pad);
+            cd.hi[k] = (float)(hi[k] + pad);
+        }
+    }
+    for (int j = tid; j < a.n_inst; j += blockDim.x) {
+        Instance &in = a.inst[j];
+        if (in.segment < 0) continue;
+        const SegDev &sg = a.segs[in.segment];
+        const float *p = a.params + 6 * in.segment;
+        double tx = p[0], ty = p[1], R = p[2];
+        double s = R / sg.r0;
+        D3 e1 = dload(sg.e1), e2 = dload(sg.e2);
+        D3 cols[3], dcx[3], dcy[3];
+        for (int c = 0; c < 3; ++c) {
+            D3 ej = D3{c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0};
+            D3 r1 = drot(e1, tx, ej);
+            cols[c] = drot(e2, ty, r1);
+            dcx[c] = drot(e2, ty, dcross(e1, r1));
+            dcy[c] = dcross(e2, cols[c]);
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double rc = r == 0 ? cols[c].x : (r == 1 ? cols[c].y : cols[c].z);
+                in.rot[3 * r + c] = (float)rc;
+                in.m[3 * c + r] = (float)(rc / s);   // (1/s) Rot^T
+                in.drx[3 * r + c] = (float)(r == 0 ? dcx[c].x : (r == 1 ? dcx[c].y : dcx[c].z));
+                in.dry[3 * r + c] = (float)(r == 0 ? dcy[c].x : (r == 1 ? dcy[c].y : dcy[c].z));
+            }
+        D3 org = dadd(dload(sg.pivot), D3{p[3], p[4], p[5]});
+        store3(in.org, org);
+        in.scale = (float)s;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int c = 0; c < 8; ++c) {
+            D3 l = D3{(c & 1) ? in.loc_hi[0] : in.loc_lo[0], (c & 2) ? in.loc_hi[1] : in.loc_lo[1],
+                      (c & 4) ? in.loc_hi[2] : in.loc_lo[2]};
+            D3 w = dadd(org, dmul(dadd(dadd(dmul(cols[0], l.x), dmul(cols[1], l.y)), dmul(cols[2], l.z)), s));
+            double q[3] = {w.x, w.y, w.z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], q[k]);
+                hi[k] = fmax(hi[k], q[k]);
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double pad = 1e-2 + 1e-6 * fmax(fabs(lo[k]), fabs(hi[k]));
+            in.lo[k] = (float)(lo[k] - pad);
+            in.hi[k] = (float)(hi[k] + pad);
+        }
+    }
+    __syncthreads();
+    __threadfence_block();
+    if (tid == 0) {
+        // children follow their parent in depth-first order: refit from the back
+        for (int i = a.n_top - 1; i >= 0; --i) {
+            Node4 &nd = a.nodes[i];
+            for (int k = 0; k < 4; ++k) {
+                uint32_t c = nd.child[k];
+                if (c == kEmpty) continue;
+                float lo[3], hi[3];
+                if (c & kLeafBit) {
+                    const Instance &in = a.inst[c & ~(kLeafBit | kInstBit)];
+                    for (int q = 0; q < 3; ++q) {
+                        lo[q] = in.lo[q];
+                        hi[q] = in.hi[q];
+                    }
+                } else {
+                    const Node4 &ch = a.nodes[c];
+                    for (int q = 0; q < 3; ++q) {
+                        lo[q] = INFINITY;
+                        hi[q] = -INFINITY;
+                    }
+                    for (int m = 0; m < 4; ++m) {
+                        if (ch.child[m] == kEmpty) continue;
+                        lo[0] = fminf(lo[0], ch.lox[m]);
+                        lo[1] = fminf(lo[1], ch.loy[m]);
+                        lo[2] = fminf(lo[2], ch.loz[m]);
+                        hi[0] = fmaxf(hi[0], ch.hix[m]);
+                        hi[1] = fmaxf(hi[1], ch.hiy[m]);
+                        hi[2] = fmaxf(hi[2], ch.hiz[m]);
+                    }
+                }
+                nd.lox[k] = lo[0];
+                nd.loy[k] = lo[1];
+                nd.loz[k] = lo[2];
+                nd.hix[k] = hi[0];
+                nd.hiy[k] = hi[1];
+                nd.hiz[k] = hi[2];
+            }
+        }
+    }
+}
+
+hipError_t launch_prepare(const PrepareArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Graph-safe zeroing of small counters (no memset node in captured graphs).
+__global__ void fill_u64_kernel(unsigned long long *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- per-photon body
+
+// Trace photon g (output slot i) and write its results.  Every lane of the
+// wave must call this together (inactive lanes with active = false): the fate
+// counters and the hit list use wave-wide ballots.
+__device__ __forceinline__ void photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
+                                           uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride) {
+    PathEnd end;
+    end.fate = -1;
+    end.pixel = -1;
+    if (active) {
+        Photon ph = make_photon(src, seed, g, i);
+        NoRecord rec;
+        propagate(S, *S.det, ph, seed, g, stk, stride, end, rec);
+        bool on_det = end.fate == kDetected || end.fate == kQeRejected;
+        if (out.fate) out.fate[i] = (uint8_t)end.fate;
+        if (out.pixel) out.pixel[i] = on_det ? end.pixel : -1;
+        if (out.hit_xyz) {
+            float *p = out.hit_xyz + 3 * i;
+            p[0] = on_det ? end.P.x : __builtin_nanf("");
+            p[1] = on_det ? end.P.y : __builtin_nanf("");
+            p[2] = on_det ? end.P.z : __builtin_nanf("");
+        }
+        if (out.hit_uv) {
+            float *p = out.hit_uv + 2 * i;
+            p[0] = on_det ? end.u : __builtin_nanf("");
+            p[1] = on_det ? end.v : __builtin_nanf("");
+        }
+        if (out.histogram && end.fate == kDetected) atomicAdd(out.histogram + end.pixel, 1u);
+    }
+    const int lane = __lane_id();
+    if (out.fate_counts) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            unsigned long long m = __ballot(end.fate == f);
+            if (lane == 0 && m) atomicAdd(out.fate_counts + f, (unsigned long long)__popcll(m));
+        }
+    }
+    if (out.hit_list) {
+        unsigned long long m = __ballot(end.fate == kDetected);
+        if (m) {
+            int leader = __ffsll((long long)m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(out.hit_count, (unsigned long long)__popcll(m));
+            uint32_t lo = __shfl((uint32_t)base, leader), hi = __shfl((uint32_t)(base >> 32), leader);
+            base = ((unsigned long long)hi << 32) | lo;
+            if (end.fate == kDetected) {
+                unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                if (slot < out.hit_capacity) {
+                    char *rec = reinterpret_cast<char *>(out.hit_list) + 24 * slot;
+                    *reinterpret_cast<uint64_t *>(rec) = g;
+                    *reinterpret_cast<int32_t *>(rec + 8) = end.pixel;
+                    float *xyz = reinterpret_cast<float *>(rec + 12);
+                    xyz[0] = end.P.x;
+                    xyz[1] = end.P.y;
+                    xyz[2] = end.P.z;
+                } else {
+                    atomicOr(S.status, 1u);  // RICH_FLAG_HITLIST_OVERFLOW
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward: one photon per lane
+
+constexpr int kForwardBlock = 256;
+
+__global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
+                                                                uint64_t first, uint64_t seed) {
+    extern __shared__ uint32_t lds_stack[];
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+}
+
+hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
+                          uint64_t seed, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + kForwardBlock - 1) / kForwardBlock;
+    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t);
+    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
+                       seed);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batch: persistent, dynamic chunks
+
+// Each wave repeatedly claims `chunk` consecutive photon ids from a global
+// counter and traces them 64 at a time until the ids run out.  Every wave
+// leaves the loop when a claim starts at or beyond n.
+__global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
+                                                    uint64_t seed, unsigned long long *counter, int chunk) {
+    extern __shared__ uint32_t lds_stack[];
+    const int lane = __lane_id();
+    uint32_t *stk = lds_stack + threadIdx.x;
+    while (true) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned long long)chunk);
+        uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
+        base = ((unsigned long long)hi << 32) | lo;
+        if (base >= n) break;
+        for (int k = 0; k < chunk; k += 64) {
+            uint64_t g = base + (uint64_t)k + (uint64_t)lane;
+            photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+        }
+    }
+}
+
+hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
+                        unsigned long long *counter, int block, int chunk, int grid, hipStream_t st) {
+    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t);
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk);
+    return hipGetLastError();
+}
+
+}  // namespace rich

@@ -1,0 +1,53 @@
+// Host representation of a librich scene (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rich.h"
+#include "rich_dev.h"
+
+struct rich_scene {
+    int device = 0;
+    int n_cu = 0;
+
+    // device memory (owned)
+    rich::Node4 *d_nodes = nullptr;
+    rich::Tri *d_tris = nullptr;
+    rich::Instance *d_inst = nullptr;
+    rich::CapDev *d_caps = nullptr;
+    rich::CapStatic *d_caps_static = nullptr;
+    rich::SegDev *d_segs = nullptr;
+    rich::RectDev *d_rects = nullptr;
+    rich::MatDev *d_mats = nullptr;
+    rich::DetDev *d_det = nullptr;
+    float *d_params = nullptr;
+    unsigned int *d_status = nullptr;
+    unsigned long long *d_counter = nullptr;   // batch work counter
+    float *d_partials = nullptr;               // adjoint per-block partial sums
+    size_t partials_floats = 0;
+
+    rich::DevScene dev{};
+    int32_t n_segments = 0;
+    int32_t n_top = 0;
+    int32_t nx = 0, ny = 0;
+    rich_scene_stats stats{};
+
+    // captured batch graph and the arguments it was captured with
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::string graph_key;
+
+    // launch shapes chosen by the autotuner, keyed by workload class
+    std::map<std::string, rich_tuning> tuned;
+};
+
+namespace rich {
+rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out);
+void free_scene(rich_scene *s);
+rich_status set_error(rich_status code, const char *fmt, ...);
+}  // namespace rich

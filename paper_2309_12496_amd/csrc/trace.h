@@ -1,0 +1,542 @@
+// Device functions of the photon path: random stream, generation, closest hit,
+// interaction.  Shared by the forward, batch and adjoint kernels.
+//
+// Precision: FP32 throughout, except the Cherenkov cone constants of batch
+// tracks (1/(n beta) and its sine, FP64 to avoid cancellation in 1 - cos^2)
+// and the rare watertight-test fallback on exactly-zero edge functions.
+#pragma once
+
+#include "rich_dev.h"
+
+namespace rich {
+
+// ---------------------------------------------------------------- vectors
+
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 ld3(const float *p) { return V3{p[0], p[1], p[2]}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return V3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return V3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) {  // s*a + b
+    return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)};
+}
+__device__ __forceinline__ V3 mat3(const float *m, V3 v) {  // row-major 3x3 times v
+    return V3{fmaf(m[0], v.x, fmaf(m[1], v.y, m[2] * v.z)), fmaf(m[3], v.x, fmaf(m[4], v.y, m[5] * v.z)),
+              fmaf(m[6], v.x, fmaf(m[7], v.y, m[8] * v.z))};
+}
+__device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+// Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64
+// multiplies whose halves are cross-mixed with the other words and the key;
+// the key advances by the Weyl constants (golden ratio, sqrt 3) each round.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
+        uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 photon_block(uint64_t seed, uint64_t g, uint32_t blk) {
+    return philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), blk, kStreamTag), (uint32_t)seed,
+                         (uint32_t)(seed >> 32));
+}
+
+// top 24 bits as a float in [0,1): exact
+__device__ __forceinline__ float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
+
+// ---------------------------------------------------------------- tables
+
+__device__ __forceinline__ float lerp_table(int n, const float *x, const float *y, float l) {
+    if (l <= x[0]) return y[0];
+    if (l >= x[n - 1]) return y[n - 1];
+    int i = 0;
+    while (i + 2 < n && l >= x[i + 1]) ++i;
+    float w = (l - x[i]) / (x[i + 1] - x[i]);
+    return fmaf(w, y[i + 1] - y[i], y[i]);
+}
+
+// ---------------------------------------------------------------- generation
+
+struct Photon {
+    V3 o, d;
+    float lambda;
+    float u_qe;
+};
+
+__device__ __forceinline__ int find_track(const uint64_t *off, int n_tracks, uint64_t g) {
+    int lo = 0, hi = n_tracks;  // last k with off[k] <= g
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Orthonormal basis (b1, b2) around unit n, after Duff et al., JCGT 2017.
+__device__ __forceinline__ void basis(V3 n, V3 &b1, V3 &b2) {
+    float sgn = copysignf(1.0f, n.z);
+    float a = -1.0f / (sgn + n.z);
+    float b = n.x * n.y * a;
+    b1 = V3{1.0f + sgn * n.x * n.x * a, sgn * b, -sgn * n.x};
+    b2 = V3{b, sgn + n.y * n.y * a, -n.y};
+}
+
+__device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t seed, uint64_t g, uint64_t i) {
+    uint4 w = photon_block(seed, g, 0);
+    Photon ph;
+    ph.u_qe = u24(w.w);
+    if (src.kind == 2) {
+        ph.o = ld3(src.ex_o + 3 * i);
+        ph.d = ld3(src.ex_d + 3 * i);
+        ph.lambda = src.ex_l[i];
+        return ph;
+    }
+    V3 P0, T, E1, E2;
+    float L, ct, st;
+    if (src.kind == 1) {
+        int k = find_track(src.offsets, src.n_tracks, g);
+        const float4 *tr = reinterpret_cast<const float4 *>(src.tracks) + 2 * k;
+        float4 a = tr[0], b = tr[1];
+        P0 = V3{a.x, a.y, a.z};
+        T = V3{a.w, b.x, b.y};
+        T = rsqrtf(dot(T, T)) * T;
+        L = b.z;
+        double c = 1.0 / (src.n_radiator * (double)b.w);
+        ct = (float)c;
+        st = (float)sqrt((1.0 - c) * (1.0 + c));
+        basis(T, E1, E2);
+    } else {
+        P0 = ld3(src.P0);
+        T = ld3(src.T);
+        E1 = ld3(src.E1);
+        E2 = ld3(src.E2);
+        L = src.length;
+        ct = src.cos_t;
+        st = src.sin_t;
+    }
+    ph.lambda = 1.0f / fmaf(-u24(w.y), src.inv_span, src.inv_lmin);
+    float sp, cp;
+    sincospif(2.0f * u24(w.x), &sp, &cp);
+    V3 d = fma3(ct, T, st * fma3(cp, E1, sp * E2));
+    ph.d = rsqrtf(dot(d, d)) * d;
+    ph.o = fma3(u24(w.z) * L, T, P0);
+    return ph;
+}
+
+// ---------------------------------------------------------------- ray state
+
+struct Ray {
+    V3 o, d;          // current frame (world or instance-local)
+    V3 inv;           // 1/d with zeros nudged away
+    V3 oi;            // o * inv
+    int kx, ky, kz;   // watertight permutation
+    float sx, sy, sz; // watertight shear
+};
+
+__device__ __forceinline__ float safe_inv(float x) {
+    return 1.0f / (fabsf(x) > 1e-30f ? x : copysignf(1e-30f, x));
+}
+
+__device__ __forceinline__ void ray_setup(Ray &r, V3 o, V3 d) {
+    r.o = o;
+    r.d = d;
+    r.inv = V3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
+    r.oi = V3{o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z};
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    float dz = comp(d, kz);
+    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.sz = 1.0f / dz;
+    r.sx = comp(d, kx) * r.sz;
+    r.sy = comp(d, ky) * r.sz;
+}
+
+// Slab test of an AABB with the robust far-distance scaling of Ize (JCGT 2013).
+__device__ __forceinline__ float slab_entry(const Ray &r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                            float tmax) {
+    float t0x = fmaf(lx, r.inv.x, -r.oi.x), t1x = fmaf(hx, r.inv.x, -r.oi.x);
+    float t0y = fmaf(ly, r.inv.y, -r.oi.y), t1y = fmaf(hy, r.inv.y, -r.oi.y);
+    float t0z = fmaf(lz, r.inv.z, -r.oi.z), t1z = fmaf(hz, r.inv.z, -r.oi.z);
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000004f;
+    tf = fminf(tf, tmax);
+    return tn <= tf ? tn : INFINITY;
+}
+
+// ---------------------------------------------------------------- closest hit
+
+struct Hit {
+    float t;
+    uint32_t prim;   // global primitive id (ties: lower wins)
+    uint32_t tri;    // triangle slot (meshes)
+    int32_t inst;    // instance of the triangle
+    int32_t root;    // sphere root taken (caps)
+};
+
+__device__ __forceinline__ bool better(float t, uint32_t prim, const Hit &h) {
+    return t < h.t || (t == h.t && prim < h.prim);
+}
+
+// Sphere cap with the cancellation-free discriminant of Haines et al.
+// (Ray Tracing Gems, ch. 7): disc = R^2 - |f - (f.d) d|^2, roots q and c/q.
+__device__ __forceinline__ bool hit_cap(const CapDev &cp, V3 o, V3 d, float tmin, float &t_out, int &root) {
+    V3 C = ld3(cp.C);
+    V3 f = o - C;
+    float b = dot(f, d);
+    V3 fp = fma3(-b, d, f);
+    float R = cp.R;
+    float disc = fmaf(R, R, -dot(fp, fp));
+    if (!(disc >= 0.0f)) return false;
+    float sq = sqrtf(disc);
+    float c = fmaf(-R, R, dot(f, f));
+    float q = -(b + copysignf(sq, b));
+    if (q == 0.0f) return false;
+    float r0 = c / q, r1 = q;
+    float ta = fminf(r0, r1), tb = fmaxf(r0, r1);
+    V3 ax = ld3(cp.axis), O = ld3(cp.O), A = ld3(cp.A), B = ld3(cp.B);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        float t = k == 0 ? ta : tb;
+        if (!(t > tmin)) continue;
+        V3 P = fma3(t, d, o);
+        if (dot(P - C, ax) >= 0.0f) continue;
+        V3 PO = P - O;
+        float a = dot(PO, A), bb = dot(PO, B);
+        if (a >= cp.a_lo && a < cp.a_hi && bb >= cp.b_lo && bb < cp.b_hi) {
+            t_out = t;
+            root = k;
+            return true;
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool hit_plane_rect(V3 c, V3 n, V3 U, V3 W, float hu, float hv, V3 o, V3 d, float tmin,
+                                               float &t_out) {
+    float dn = dot(d, n);
+    if (dn == 0.0f) return false;
+    V3 co = c - o;
+    float t = dot(co, n) / dn;
+    if (!(t > tmin)) return false;
+    V3 Pc = fma3(t, d, o - c);
+    float u = dot(Pc, U), v = dot(Pc, W);
+    if (fabsf(u) <= hu && fabsf(v) <= hv) {
+        t_out = t;
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool hit_box(const float *lo, const float *hi, V3 o, V3 d, float tmin, float &t_out) {
+    float tn = -INFINITY, tf = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float oa = comp(o, a), da = comp(d, a);
+        if (da == 0.0f) {
+            if (oa < lo[a] || oa > hi[a]) return false;
+            continue;
+        }
+        float t1 = (lo[a] - oa) / da, t2 = (hi[a] - oa) / da;
+        tn = fmaxf(tn, fminf(t1, t2));
+        tf = fminf(tf, fmaxf(t1, t2));
+    }
+    if (tn > tf) return false;
+    if (tn > tmin) { t_out = tn; return true; }
+    if (tf > tmin) { t_out = tf; return true; }
+    return false;
+}
+
+// Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013), two-sided.
+__device__ __forceinline__ bool hit_tri(const Ray &r, const float4 &a, const float4 &b, const float4 &c, float tmin,
+                                        float &t_out) {
+    V3 A = V3{a.x, a.y, a.z} - r.o, B = V3{b.x, b.y, b.z} - r.o, C = V3{c.x, c.y, c.z} - r.o;
+    float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
+    float Ax = fmaf(-r.sx, Akz, comp(A, r.kx)), Ay = fmaf(-r.sy, Akz, comp(A, r.ky));
+    float Bx = fmaf(-r.sx, Bkz, comp(B, r.kx)), By = fmaf(-r.sy, Bkz, comp(B, r.ky));
+    float Cx = fmaf(-r.sx, Ckz, comp(C, r.kx)), Cy = fmaf(-r.sy, Ckz, comp(C, r.ky));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = U + V + W;
+    if (det == 0.0f) return false;
+    float T = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
+    float t = T / det;
+    if (!(t > tmin)) return false;
+    t_out = t;
+    return true;
+}
+
+__device__ __forceinline__ void to_frame(Ray &r, const Instance &in, V3 ow, V3 dw) {
+    V3 o = mat3(in.m, ow - ld3(in.org));
+    V3 d = mat3(in.m, dw);
+    ray_setup(r, o, d);
+}
+
+// Closest triangle along (ow, dw) with t < h.t, through the two-level BVH4.
+// stk points at this lane's first LDS stack slot; entries are `stride` apart.
+__device__ __forceinline__ void traverse(const DevScene &S, V3 ow, V3 dw, Hit &h, uint32_t *stk, int stride) {
+    Ray r;
+    ray_setup(r, ow, dw);
+    int inst = -1;
+    int sp = 0;
+    uint32_t ref = S.top_root;
+    const float tmin = S.t_min;
+    while (true) {
+        if (!(ref & kLeafBit)) {
+            const Node4 &nd = S.nodes[ref];
+            float4 lx = *reinterpret_cast<const float4 *>(nd.lox);
+            float4 hx = *reinterpret_cast<const float4 *>(nd.hix);
+            float4 ly = *reinterpret_cast<const float4 *>(nd.loy);
+            float4 hy = *reinterpret_cast<const float4 *>(nd.hiy);
+            float4 lz = *reinterpret_cast<const float4 *>(nd.loz);
+            float4 hz = *reinterpret_cast<const float4 *>(nd.hiz);
+            uint4 ch = *reinterpret_cast<const uint4 *>(nd.child);
+            float tmax = h.t;
+            float d0 = slab_entry(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmax);
+            float d1 = slab_entry(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmax);
+            float d2 = slab_entry(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmax);
+            float d3 = slab_entry(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmax);
+            uint32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+            // empty slots have inverted boxes, which a min/max slab test would accept
+            if (c0 == kEmpty) d0 = INFINITY;
+            if (c1 == kEmpty) d1 = INFINITY;
+            if (c2 == kEmpty) d2 = INFINITY;
+            if (c3 == kEmpty) d3 = INFINITY;
+            // sort the four (distance, child) pairs ascending: 5 compare-exchanges
+#define RICH_CX(da, ca, db, cb)                                  \
+    if (db < da) {                                               \
+        float tf_ = da; da = db; db = tf_;                       \
+        uint32_t tc_ = ca; ca = cb; cb = tc_;                    \
+    }
+            RICH_CX(d0, c0, d1, c1);
+            RICH_CX(d2, c2, d3, c3);
+            RICH_CX(d0, c0, d2, c2);
+            RICH_CX(d1, c1, d3, c3);
+            RICH_CX(d1, c1, d2, c2);
+#undef RICH_CX
+            if (d0 == INFINITY) {
+                if (sp == 0) break;
+                ref = stk[(--sp) * stride];
+                continue;
+            }
+            int need = (d1 != INFINITY) + (d2 != INFINITY) + (d3 != INFINITY);
+            if (sp + need > kStackDepth) {
+                atomicOr(S.status, 2u);  // RICH_FLAG_STACK_OVERFLOW
+                need = kStackDepth - sp;
+            }
+            if (need >= 3) stk[(sp++) * stride] = c3;
+            if (need >= 2) stk[(sp++) * stride] = c2;
+            if (need >= 1) stk[(sp++) * stride] = c1;
+            ref = c0;
+            continue;
+        }
+        if (ref == kExitMarker) {
+            ray_setup(r, ow, dw);
+            inst = -1;
+        } else if (ref & kInstBit) {
+            int k = (int)(ref & ~(kLeafBit | kInstBit));
+            if (sp + 1 > kStackDepth) {
+                atomicOr(S.status, 2u);
+            } else {
+                stk[(sp++) * stride] = kExitMarker;
+                const Instance &in = S.inst[k];
+                to_frame(r, in, ow, dw);
+                inst = k;
+                ref = in.root;
+                continue;
+            }
+        } else {
+            uint32_t first = ref & 0x07FFFFFFu;
+            uint32_t cnt = ((ref >> 27) & 7u) + 1u;
+            for (uint32_t q = first; q < first + cnt; ++q) {
+                const float4 *tp = reinterpret_cast<const float4 *>(S.tris + q);
+                float4 a = tp[0], b = tp[1], c = tp[2];
+                float t;
+                if (hit_tri(r, a, b, c, tmin, t)) {
+                    uint32_t prim = S.prim_tri + __float_as_uint(a.w);
+                    if (better(t, prim, h)) {
+                        h.t = t;
+                        h.prim = prim;
+                        h.tri = q;
+                        h.inst = inst;
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        ref = stk[(--sp) * stride];
+    }
+}
+
+__device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det, V3 o, V3 d, Hit &h, uint32_t *stk,
+                                            int stride) {
+    h.t = INFINITY;
+    h.prim = 0xFFFFFFFFu;
+    h.tri = 0;
+    h.inst = -1;
+    h.root = 0;
+    const float tmin = S.t_min;
+    float t;
+    if (S.n_caps > 0) {
+        Ray r;
+        ray_setup(r, o, d);
+        for (int i = 0; i < S.n_caps; ++i) {
+            const CapDev &cp = S.caps[i];
+            if (slab_entry(r, cp.lo[0], cp.lo[1], cp.lo[2], cp.hi[0], cp.hi[1], cp.hi[2], h.t) == INFINITY) continue;
+            int root;
+            if (hit_cap(cp, o, d, tmin, t, root) && better(t, (uint32_t)i, h)) {
+                h.t = t;
+                h.prim = (uint32_t)i;
+                h.root = root;
+            }
+        }
+    }
+    for (int i = 0; i < S.n_rects; ++i) {
+        const RectDev &rc = S.rects[i];
+        if (hit_plane_rect(ld3(rc.c), ld3(rc.n), ld3(rc.u), ld3(rc.v), rc.hu, rc.hv, o, d, tmin, t) &&
+            better(t, (uint32_t)(S.n_caps + i), h)) {
+            h.t = t;
+            h.prim = (uint32_t)(S.n_caps + i);
+        }
+    }
+    if (hit_plane_rect(ld3(det.c), ld3(det.n), ld3(det.u), ld3(det.v), det.hu, det.hv, o, d, tmin, t) &&
+        better(t, S.prim_det, h)) {
+        h.t = t;
+        h.prim = S.prim_det;
+    }
+    if (S.has_box && hit_box(S.box_lo, S.box_hi, o, d, tmin, t) && better(t, S.prim_box, h)) {
+        h.t = t;
+        h.prim = S.prim_box;
+    }
+    if (S.has_mesh) traverse(S, o, d, h, stk, stride);
+}
+
+// ---------------------------------------------------------------- interaction
+
+constexpr int kDetected = 0, kQeRejected = 1, kAbsorbedMirror = 2, kAbsorbed = 3, kEscaped = 4, kMaxBounces = 5;
+
+struct PathEnd {
+    int fate;
+    int pixel;
+    V3 P;
+    float u, v;
+};
+
+// Receives every reflection and the detector hit; the forward kernels ignore them.
+struct NoRecord {
+    __device__ __forceinline__ void reflect(int b, const Hit &h, V3 o, V3 d, V3 P, V3 n) {}
+    __device__ __forceinline__ void detect(int b, V3 o, V3 d, float t) {}
+};
+
+__device__ __forceinline__ V3 surface_normal(const DevScene &S, const Hit &h, V3 P, int &mat) {
+    if (h.prim < (uint32_t)S.n_caps) {
+        const CapDev &cp = S.caps[h.prim];
+        mat = cp.material;
+        return (1.0f / cp.R) * (ld3(cp.C) - P);
+    }
+    if (h.prim < S.prim_det) {
+        const RectDev &rc = S.rects[h.prim - S.n_caps];
+        mat = rc.material;
+        return ld3(rc.n);
+    }
+    const Tri &tr = S.tris[h.tri];
+    mat = (int)tr.material;
+    V3 n = ld3(tr.n);
+    if (h.inst >= 0 && S.inst[h.inst].segment >= 0) n = mat3(S.inst[h.inst].rot, n);
+    return n;
+}
+
+template <class Rec>
+__device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, const Photon &ph, uint64_t seed,
+                                          uint64_t g, uint32_t *stk, int stride, PathEnd &end, Rec &rec) {
+    V3 o = ph.o, d = ph.d;
+    end.fate = kMaxBounces;
+    end.pixel = -1;
+    uint4 blk = make_uint4(0, 0, 0, 0);
+    int have = -1;
+    for (int b = 0; b < S.max_bounces; ++b) {
+        Hit h;
+        closest_hit(S, det, o, d, h, stk, stride);
+        if (h.prim == 0xFFFFFFFFu) {
+            end.fate = kEscaped;
+            break;
+        }
+        if (h.prim == S.prim_det) {
+            if (dot(d, ld3(det.n)) >= 0.0f) {
+                end.fate = kAbsorbed;
+                break;
+            }
+            V3 Pc = fma3(h.t, d, o - ld3(det.c));
+            float u = dot(Pc, ld3(det.u)), v = dot(Pc, ld3(det.v));
+            float fi = floorf((u + det.act_hu) / det.pitch), fj = floorf((v + det.act_hv) / det.pitch);
+            if (!(fi >= 0.0f && fi < (float)det.nx && fj >= 0.0f && fj < (float)det.ny)) {  // NaN-safe
+                end.fate = kAbsorbed;
+                break;
+            }
+            end.pixel = (int)fj * det.nx + (int)fi;
+            end.P = fma3(h.t, d, o);
+            end.u = u;
+            end.v = v;
+            rec.detect(b, o, d, h.t);
+            float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, ph.lambda);
+            end.fate = ph.u_qe < qe ? kDetected : kQeRejected;
+            break;
+        }
+        if (h.prim == S.prim_box) {
+            end.fate = kAbsorbed;
+            break;
+        }
+        V3 P = fma3(h.t, d, o);
+        int mat;
+        V3 n = surface_normal(S, h, P, mat);
+        const MatDev &m = S.mats[mat];
+        if (m.kind != 0 || dot(d, n) >= 0.0f) {
+            end.fate = kAbsorbed;
+            break;
+        }
+        int bid = 1 + (b >> 2);
+        if (have != bid) {
+            blk = photon_block(seed, g, (uint32_t)bid);
+            have = bid;
+        }
+        int w = b & 3;
+        uint32_t word = w == 0 ? blk.x : (w == 1 ? blk.y : (w == 2 ? blk.z : blk.w));
+        float refl = lerp_table(m.n, m.x, m.y, ph.lambda);
+        if (u24(word) >= refl) {
+            end.fate = kAbsorbedMirror;
+            break;
+        }
+        rec.reflect(b, h, o, d, P, n);
+        V3 dr = fma3(-2.0f * dot(d, n), n, d);
+        d = rsqrtf(dot(dr, dr)) * dr;
+        o = P;
+    }
+}
+
+}  // namespace rich
