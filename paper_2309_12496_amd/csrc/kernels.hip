@@ -120,6 +120,7 @@ __global__ void prepare_kernel(PrepareArgs a) {
         D3 org = dadd(dload(sg.pivot), D3{p[3], p[4], p[5]});
         store3(in.org, org);
         in.scale = (float)s;
+        in.inv_r0 = (float)(1.0 / sg.r0);
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         for (int c = 0; c < 8; ++c) {
             D3 l = D3{(c & 1) ? in.loc_hi[0] : in.loc_lo[0], (c & 2) ? in.loc_hi[1] : in.loc_lo[1],

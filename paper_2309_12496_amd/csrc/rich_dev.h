@@ -64,7 +64,8 @@ struct alignas(16) Instance {
     float loc_lo[3], loc_hi[3];  // local AABB
     float drx[9];        // d rot / d tilt_x (for the adjoint)
     float dry[9];        // d rot / d tilt_y
-    float pad[2];
+    float inv_r0;        // 1 / nominal radius of the segment (0 for fixed meshes)
+    float pad;
 };
 
 // Analytic spherical cap at the current parameters.

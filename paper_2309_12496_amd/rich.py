@@ -435,3 +435,38 @@ def propagate_batch(scene, src, seed, tune=None, hit_list_capacity=0, stream=Non
 
 def tuning(block, chunk, blocks_per_cu):
     return rich_tuning(int(block), int(chunk), int(blocks_per_cu), 0)
+
+
+def adjoint(scene, src, seed, n=None, first_id=0, grad_uv=None, targets=None, mask=None, stream=None):
+    """Reverse-mode gradient of the hits w.r.t. the segment parameters at the scene's current parameters.
+
+    Exactly one of grad_uv ([N,2] upstream dL/d(u,v)) and targets ([N,2], fused mean-squared loss) is
+    given.  Returns (grad [n_segments, 6] float32 tensor, loss [1] tensor).
+    """
+    device = f"cuda:{scene.device}"
+    keep = []
+    if src["kind"] == "batch":
+        b, keep, nb = make_batch(src, device)
+        s = None
+        n = nb if n is None else n
+    else:
+        s, keep = make_source(src, device)
+        b = None
+    if n is None:
+        raise ValueError("n is required for single sources")
+
+    def dev(x, dtype):
+        if x is None:
+            return None
+        t = x if torch.is_tensor(x) else torch.as_tensor(np.asarray(x))
+        return t.to(device=device, dtype=dtype).contiguous()
+
+    gu = dev(grad_uv, torch.float32)
+    tg = dev(targets, torch.float32)
+    mk = dev(mask, torch.uint8)
+    grad = torch.zeros((scene.n_segments, 6), dtype=torch.float32, device=device)
+    loss = torch.zeros(1, dtype=torch.float32, device=device)
+    rich_propagate_adjoint(scene.handle, s, b, n, seed, first_id, gu, tg, mk, grad, loss, stream)
+    keep += [gu, tg, mk]
+    grad._keep = keep
+    return grad, loss

@@ -1,0 +1,186 @@
+"""GPU parity of rich_set_mirror_params and rich_propagate_adjoint against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from paper_2309_12496_amd import inputs as I
+from parity import compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+GRAD_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2309_12496_amd import rich
+    return rich
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    return oracle
+
+
+def grad_close(g, ref, rtol=GRAD_RTOL, label=""):
+    """|g - g*| / |g*| <= rtol overall and per component with |g*_j| >= 1e-2 max|g*|."""
+    g = np.asarray(g, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    norm = np.linalg.norm(ref)
+    assert norm > 0, label
+    rel = np.linalg.norm(g - ref) / norm
+    big = np.abs(ref) >= 1e-2 * np.abs(ref).max()
+    per = np.abs(g[big] - ref[big]) / np.abs(ref[big])
+    assert rel <= rtol and per.max() <= rtol, f"{label} rel {rel:.2e} worst component {per.max():.2e}"
+    return rel, per.max()
+
+
+def c4_problem(orc, n_tracks, per_track, meshed=False):
+    if meshed:
+        scene = I.scene_g5(seg_quads=(30, 50), flat_tiles=4)
+        k = 5
+    else:
+        scene = I.scene_g4()
+        k = 4
+    rng = np.random.default_rng(1000 + k)
+    src = I.batch_source(I.sample_tracks(rng, n_tracks), np.full(n_tracks, per_track))
+    n = n_tracks * per_track
+    seed = I.SEED_BASE + k
+    tgt_params = I.perturbed_params(k, scene)
+    target = orc.propagate(orc.Scene(scene, params=tgt_params), src, n, seed)
+    cur = orc.propagate(orc.Scene(scene), src, n, seed, jacobian=True)
+    on = lambda r: np.isin(r["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    mask = on(target) & on(cur) & (target["edge_margin"] > 0.05) & (cur["edge_margin"] > 0.05)
+    loss, grad, nuse = orc.mse_loss_and_grad(cur, target["hit_uv"], mask, scene["params"].shape[0])
+    return {"scene": scene, "src": src, "n": n, "seed": seed, "target": target, "cur": cur, "mask": mask,
+            "loss": loss, "grad": grad, "nuse": nuse, "tgt_params": tgt_params}
+
+
+@pytest.fixture(scope="module")
+def c4small(orc):
+    return c4_problem(orc, 100, 1000)
+
+
+def test_perturbed_forward_matches_oracle(R, orc, c4small):
+    """rich_set_mirror_params moves the caps exactly as the oracle does."""
+    p = c4small
+    gs = R.Scene(p["scene"])
+    gs.set_params(p["tgt_params"])
+    out = R.propagate_batch(gs, p["src"], p["seed"], tune=R.tuning(256, 256, 4))
+    compare(out, p["target"], label="G4 perturbed")
+
+
+def test_fused_loss_gradient_matches_oracle(R, orc, c4small):
+    p = c4small
+    gs = R.Scene(p["scene"])
+    grad, loss = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    assert gs.status() == 0
+    assert abs(float(loss) / p["loss"] - 1) < 1e-4
+    grad_close(to_np(grad), p["grad"], label="fused")
+
+
+def test_upstream_gradient_mode_matches_oracle(R, orc, c4small):
+    p = c4small
+    rng = np.random.default_rng(3)
+    gin = rng.normal(size=(p["n"], 2))
+    gs = R.Scene(p["scene"])
+    grad, _ = R.adjoint(gs, p["src"], p["seed"], grad_uv=gin, mask=p["mask"])
+    cur = p["cur"]
+    want = np.zeros_like(p["grad"])
+    use = p["mask"] & (cur["segment"] >= 0)
+    np.add.at(want, cur["segment"][use], np.einsum("nk,nkp->np", I.f32(gin)[use], cur["jac"][use]))
+    grad_close(to_np(grad), want, label="grad_uv")
+
+
+def test_gradient_is_deterministic(R, c4small):
+    p = c4small
+    gs = R.Scene(p["scene"])
+    g1, l1 = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    g2, l2 = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    assert np.array_equal(to_np(g1), to_np(g2)) and float(l1) == float(l2)
+
+
+def test_gpu_finite_differences_fp32(R, c4small):
+    """Central differences of the GPU's own FP32 forward loss agree with its adjoint at 1e-2."""
+    import torch
+    p = c4small
+    gs = R.Scene(p["scene"])
+    grad, loss0 = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    g = to_np(grad)
+    tgt = torch.as_tensor(I.f32(p["target"]["hit_uv"]), device="cuda", dtype=torch.float32)
+    m = torch.as_tensor(p["mask"], device="cuda")
+
+    def L(params):
+        gs.set_params(params)
+        out = R.propagate_batch(gs, p["src"], p["seed"], tune=R.tuning(256, 256, 4))
+        d = out["hit_uv"].double() - tgt.double()
+        ok = m & torch.isfinite(d).all(1)
+        return float((d[ok] ** 2).sum() / m.sum())
+
+    p0 = p["scene"]["params"].astype(np.float64)
+    steps = np.array([1e-5, 1e-5, 0.02, 0.01, 0.01, 0.01])
+    k = int(np.argmax(np.abs(g).sum(1)))
+    for j in range(6):
+        pp, pm = p0.copy(), p0.copy()
+        pp[k, j] += steps[j]
+        pm[k, j] -= steps[j]
+        fd = (L(pp) - L(pm)) / (2 * steps[j])
+        assert abs(fd - g[k, j]) <= 1e-2 * np.abs(g[k]).max(), (k, j, fd, g[k, j])
+
+
+def test_autograd_function_matches_fused_mode(R, c4small):
+    import torch
+    from paper_2309_12496_amd import align
+    p = c4small
+    gs = R.Scene(p["scene"])
+    b, keep, n = R.make_batch(p["src"])
+    # the autograd path uses single-source calls: check on the batch track with the most detector hits
+    offs = np.asarray(p["src"]["offsets"], np.int64)
+    per_track = np.add.reduceat(p["mask"].astype(np.int64), offs[:-1])
+    kt = int(np.argmax(per_track))
+    assert per_track[kt] > 50
+    tr = p["src"]["tracks"][kt]
+    src = I.point_source(origin=tr[0:3], direction=tr[3:6], beta=tr[7], length=tr[6])
+    cnt = int(offs[kt + 1] - offs[kt])
+    params = torch.tensor(I.f32(p["scene"]["params"]), device="cuda", dtype=torch.float32, requires_grad=True)
+    uv, fate = align.hits(params, gs, src, cnt, p["seed"])
+    on = (fate == 0) | (fate == 1)
+    # the photons of this single-source call are ids 0..cnt-1, so the batch targets serve as arbitrary targets
+    tgt = torch.as_tensor(I.f32(p["target"]["hit_uv"][offs[kt]:offs[kt + 1]]), device="cuda", dtype=torch.float32)
+    use = on & torch.isfinite(tgt).all(1)
+    assert int(use.sum()) > 20
+    loss = ((uv[use] - tgt[use]) ** 2).sum() / use.sum()
+    loss.backward()
+    gref, lref = R.adjoint(gs, src, p["seed"], n=cnt, targets=tgt.nan_to_num(0.0), mask=use.to(torch.uint8))
+    assert abs(float(loss) - float(lref)) <= 1e-5 * abs(float(lref))
+    grad_close(params.grad.cpu().numpy(), to_np(gref), rtol=1e-5, label="autograd")
+
+
+def test_c4_full_size_gradient(R, orc):
+    """The 1e6-photon adjoint (1000 tracks x 1000 photons, 96 parameters) against the oracle."""
+    cfg = I.config(4)
+    p = c4_problem(orc, 1000, 1000)
+    gs = R.Scene(cfg["scene"])
+    grad, loss = R.adjoint(gs, cfg["source"], cfg["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    assert gs.status() == 0
+    assert abs(float(loss) / p["loss"] - 1) < 1e-4
+    rel, worst = grad_close(to_np(grad), p["grad"], label="C4 full")
+    print({"nuse": p["nuse"], "rel": rel, "worst": worst})
+
+
+def test_meshed_segments_forward_and_gradient(R, orc):
+    """Meshed mirror segments moved through their instance transforms; gradient through facets."""
+    p = c4_problem(orc, 150, 400, meshed=True)
+    gs = R.Scene(p["scene"])
+    gs.set_params(p["tgt_params"])
+    out = R.propagate_batch(gs, p["src"], p["seed"], tune=R.tuning(256, 256, 4))
+    compare(out, p["target"], label="G5-small perturbed")
+    gs.set_params(p["scene"]["params"])
+    grad, loss = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"])
+    assert gs.status() == 0
+    assert abs(float(loss) / p["loss"] - 1) < 1e-4
+    grad_close(to_np(grad), p["grad"], label="meshed")
