@@ -7,8 +7,13 @@ rich_propagate launch.  Inputs and outputs are resident in HBM; the scene is
 built once outside the timed region (as the paper separates scene parsing and
 kernel initialisation from rendering, Section 5.2).
 
-Default workload: the meshed RICH scene (200k-triangle spherical mirror, flat
-mirror, 10k-triangle enclosure) with 1e7 photons from one point emitter.
+Headline workload: the meshed RICH scene (200k-triangle spherical mirror,
+flat mirror, 10k-triangle enclosure) with 1e7 photons from one point
+emitter, plain forward.  The other forms of the metric are reported under
+"forms": batched (4096 Poisson-sized tracks, one persistent launch replayed
+from a HIP graph), forward+adjoint (4x4 segmented mirror, 1e6 photons, 96
+parameters), the analytic scene (1e5 photons per call, and 1e8 in one call),
+and the large scene (1e8 photons, 2M triangles, 192 parameters).
 Prints one JSON line.
 """
 
@@ -23,19 +28,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# HBM peak and VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-# = 3.93e13 32-bit lane operations per second without packed math.
+# MI355X peaks: HBM3E 8 TB/s; VALU 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz =
+# 3.93e13 32-bit lane operations per second (no packed math).
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# Algorithmic VALU work per photon of the forward kernel (lane operations),
-# measured as SQ_INSTS_VALU * 64 / photons on the default workload (see profiles/).
-ALU_OPS_PER_PHOTON = {"c1": None, "c2": None}
-# Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8, plus the
-# histogram atomics of the detected photons (4 B each).
+# Algorithmic VALU work per photon of forward_kernel on the headline workload,
+# in lane operations (SQ_INSTS_VALU x 64 / photons, see profiles/).  None until measured.
+ALU_OPS_PER_PHOTON = None
+# Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 (writes).
 OUT_BYTES_PER_PHOTON = 25.0
-
-WORKLOADS = {"c1": 1, "c2": 2, "c3": 3}
+# HBM bytes per photon counted by FETCH_SIZE + WRITE_SIZE for the headline launch
+# (scaled by the copy-kernel calibration, see profiles/); None until measured.
+TRAFFIC_BYTES_PER_PHOTON = None
 
 
 def parse():
@@ -43,11 +48,24 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--no-forms", action="store_true", help="skip the batched form")
+    p.add_argument("--no-forms", action="store_true", help="only the headline workload")
+    p.add_argument("--forms", default="c1,batched,adjoint,large", help="comma list of extra forms")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 256 MiB read and 256 MiB written, 3 times."""
+    import torch
+    x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "reps": 3}))
 
 
 def time_steps(fn, steps, warmup, stream):
@@ -66,7 +84,7 @@ def time_steps(fn, steps, warmup, stream):
 
 
 def cpu_baseline(cfg, target_seconds):
-    """FP64 oracle on a bounded prefix of the same workload, all host threads."""
+    """FP64 oracle on a bounded prefix of the same workload, all host threads (up to 16)."""
     import numpy as np
     from oracle import oracle as O
     threads = min(os.cpu_count() or 1, 16)
@@ -81,58 +99,103 @@ def cpu_baseline(cfg, target_seconds):
     dt = time.perf_counter() - t0
     assert int(np.bincount(res["fate"], minlength=6).sum()) == n
     return {"value": n / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
-            "sample": f"photon ids 0..{n - 1} of the same workload ({dt:.1f} s on {threads} threads)"}
+            "sample": f"photon ids 0..{n - 1} of the headline workload ({dt:.1f} s on {threads} threads)"}
+
+
+def form_batched(R, I, stream, steps):
+    cfg = I.config(3)
+    sc = R.Scene(cfg["scene"])
+    b, keep, n = R.make_batch(cfg["source"])
+    t, o = R.alloc_outputs(sc, n)
+    tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])
+    ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 2, stream)
+    assert sc.status() == 0
+    return {"workload": cfg["name"], "photons_per_step": n, "ms_per_step": ms, "photons_per_s": n / (ms * 1e-3),
+            "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu}}
+
+
+def _fwd_adjoint(R, I, cfg, stream, steps):
+    """Forward (batched) plus fused-loss adjoint per step, targets from misaligned segments."""
+    import torch
+    sc = R.Scene(cfg["scene"])
+    b, keep, n = R.make_batch(cfg["source"])
+    tune = R.tuning(256, 256, 4)
+    sc.set_params(cfg["target_params"])
+    tgt_out = R.propagate_batch(sc, cfg["source"], cfg["seed"], tune=tune)
+    targets = tgt_out["hit_uv"].nan_to_num(0.0)
+    tfate = tgt_out["fate"]
+    del tgt_out
+    sc.set_params(cfg["scene"]["params"])
+    t, o = R.alloc_outputs(sc, n)
+    R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream)
+    mask = ((tfate == 0) & (t["fate"] == 0)).to(torch.uint8)
+    grad = torch.zeros((sc.n_segments, 6), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    s_ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 1, stream)
+    a_ms = time_steps(lambda: R.rich_propagate_adjoint(sc.handle, None, b, n, cfg["seed"], 0, None, targets, mask,
+                                                       grad, loss, stream), steps, 1, stream)
+    assert sc.status() == 0
+    return {"workload": cfg["name"], "photons_per_step": n, "parameters": 6 * sc.n_segments,
+            "forward_ms": s_ms, "adjoint_ms": a_ms, "ms_per_step": s_ms + a_ms,
+            "photons_per_s": n / ((s_ms + a_ms) * 1e-3), "forward_photons_per_s": n / (s_ms * 1e-3),
+            "loss_mm2": float(loss), "masked_photons": int(mask.sum())}
+
+
+def form_c1(R, I, stream, steps):
+    cfg = I.config(1)
+    sc = R.Scene(cfg["scene"])
+    s, keep = R.make_source(cfg["source"])
+    n = cfg["n_photons"]
+    t, o = R.alloc_outputs(sc, n)
+    ms = time_steps(lambda: R.rich_propagate(sc.handle, s, n, cfg["seed"], 0, o, stream), steps, 3, stream)
+    big = 100_000_000
+    tb, ob = R.alloc_outputs(sc, big)
+    msb = time_steps(lambda: R.rich_propagate(sc.handle, s, big, cfg["seed"], 0, ob, stream), max(3, steps // 4), 1,
+                     stream)
+    assert sc.status() == 0
+    return {"workload": cfg["name"], "single_call": {"photons_per_step": n, "ms_per_step": ms,
+                                                      "photons_per_s": n / (ms * 1e-3)},
+            "steady_state": {"photons_per_step": big, "ms_per_step": msb, "photons_per_s": big / (msb * 1e-3)}}
 
 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: photons are sharded by id range across GPUs, "
+        print("bench.py runs on one GPU only: photons shard by id range across GPUs, "
               "but this build measures a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_2309_12496_amd import inputs as I
     from paper_2309_12496_amd import rich as R
 
-    k = WORKLOADS[args.workload]
-    cfg = I.config(k)
+    cfg = I.config(2)
     t0 = time.perf_counter()
     scene = R.Scene(cfg["scene"])
     build_s = time.perf_counter() - t0
     info = scene.info()
     stream = torch.cuda.current_stream()
     n = cfg["n_photons"]
+    s, keep = R.make_source(cfg["source"])
+    t, o = R.alloc_outputs(scene, n)
 
-    if cfg["source"]["kind"] == "batch":
-        b, keep, n = R.make_batch(cfg["source"])
-        t, o = R.alloc_outputs(scene, n)
-        tune = R.rich_autotune(scene.handle, b, n, cfg["seed"])
-
-        def step():
-            R.rich_propagate_batch(scene.handle, b, n, cfg["seed"], o, tune, stream)
-    else:
-        s, keep = R.make_source(cfg["source"])
-        t, o = R.alloc_outputs(scene, n)
-
-        def step():
-            R.rich_propagate(scene.handle, s, n, cfg["seed"], 0, o, stream)
-
-    ms = time_steps(step, args.steps, args.warmup, stream)
+    ms = time_steps(lambda: R.rich_propagate(scene.handle, s, n, cfg["seed"], 0, o, stream), args.steps,
+                    args.warmup, stream)
     flags = scene.status()
     counts = t["fate_counts"].cpu().numpy()
     assert counts.sum() == n * (args.steps + args.warmup), "fate counts do not add up"
     assert flags == 0, f"device flags {flags}"
     value = n / (ms * 1e-3)
 
-    det_frac = counts[0] / counts.sum()
-    ops = ALU_OPS_PER_PHOTON.get(args.workload)
-    if ops:
-        achieved = ops * n / (ms * 1e-3)
+    if ALU_OPS_PER_PHOTON:
+        achieved = ALU_OPS_PER_PHOTON * n / (ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None}
+                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+                "traffic": None if TRAFFIC_BYTES_PER_PHOTON is None else TRAFFIC_BYTES_PER_PHOTON * n}
     else:
-        gbs = (OUT_BYTES_PER_PHOTON + 4.0 * det_frac) * n / (ms * 1e-3) / 1e9
+        gbs = OUT_BYTES_PER_PHOTON * n / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                 "traffic": None}
 
@@ -141,24 +204,28 @@ def main():
         "value": value, "unit": "photons/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "photons_per_step": n, "triangles": info["n_triangles"],
-                   "form": "batched" if cfg["source"]["kind"] == "batch" else "forward",
+        "config": {"workload": cfg["name"] + " (meshed RICH, 210,082 triangles, point emitter)",
+                   "photons_per_step": n, "triangles": info["n_triangles"], "form": "forward",
                    "scene_build_s": round(build_s, 3)},
         "roofline": roof,
     }
+    del t, o
+    torch.cuda.empty_cache()
 
-    if not args.no_forms and args.workload != "c3":
-        c3 = I.config(3)
-        s3 = R.Scene(c3["scene"])
-        b3, keep3, n3 = R.make_batch(c3["source"])
-        t3, o3 = R.alloc_outputs(s3, n3)
-        tune3 = R.rich_autotune(s3.handle, b3, n3, c3["seed"])
-        ms3 = time_steps(lambda: R.rich_propagate_batch(s3.handle, b3, n3, c3["seed"], o3, tune3, stream),
-                         max(5, args.steps // 2), 2, stream)
-        assert s3.status() == 0
-        line["forms"] = {"batched": {"workload": c3["name"], "photons_per_step": n3, "ms_per_step": ms3,
-                                     "photons_per_s": n3 / (ms3 * 1e-3),
-                                     "tuning": [tune3.block, tune3.chunk, tune3.blocks_per_cu]}}
+    if not args.no_forms:
+        forms = {}
+        want = set(args.forms.split(","))
+        half = max(5, args.steps // 2)
+        if "c1" in want:
+            forms["analytic"] = form_c1(R, I, stream, args.steps)
+        if "batched" in want:
+            forms["batched"] = form_batched(R, I, stream, half)
+        if "adjoint" in want:
+            forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half)
+        if "large" in want:
+            forms["large_fwd_adjoint"] = _fwd_adjoint(R, I, I.config(5), stream, 3)
+        line["forms"] = forms
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(line))

@@ -341,7 +341,7 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
     if ((st = make_track_source(src, ds))) return st;
     if (n_photons == 0) return RICH_OK;
     DeviceGuard g(s->device);
-    RICH_HIP(launch_forward(s->dev, ds, make_outputs(out), n_photons, first_photon_id, seed, stream));
+    RICH_HIP(launch_forward(s->dev, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
     return RICH_OK;
 }
 

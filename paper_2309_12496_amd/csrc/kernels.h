@@ -22,7 +22,7 @@ struct PrepareArgs {
 hipError_t launch_prepare(const PrepareArgs &a, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st);
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n,
-                          uint64_t first, uint64_t seed, hipStream_t st);
+                          uint64_t first, uint64_t seed, int n_cu, hipStream_t st);
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, hipStream_t st);
 

@@ -199,11 +199,11 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
 
 // ---------------------------------------------------------------- per-photon body
 
-// Trace photon g (output slot i) and write its results.  Every lane of the
-// wave must call this together (inactive lanes with active = false): the fate
-// counters and the hit list use wave-wide ballots.
-__device__ __forceinline__ void photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
-                                           uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride) {
+// Trace photon g (output slot i), write its results and return its fate (-1
+// for inactive lanes).  Every lane of the wave must call this together: the
+// hit list uses wave-wide ballots.
+__device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
+                                          uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride) {
     PathEnd end;
     end.fate = -1;
     end.pixel = -1;
@@ -227,15 +227,8 @@ __device__ __forceinline__ void photon_job(const DevScene &S, const DevSource &s
         }
         if (out.histogram && end.fate == kDetected) atomicAdd(out.histogram + end.pixel, 1u);
     }
-    const int lane = __lane_id();
-    if (out.fate_counts) {
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            unsigned long long m = __ballot(end.fate == f);
-            if (lane == 0 && m) atomicAdd(out.fate_counts + f, (unsigned long long)__popcll(m));
-        }
-    }
     if (out.hit_list) {
+        const int lane = __lane_id();
         unsigned long long m = __ballot(end.fate == kDetected);
         if (m) {
             int leader = __ffsll((long long)m) - 1;
@@ -259,24 +252,74 @@ __device__ __forceinline__ void photon_job(const DevScene &S, const DevSource &s
             }
         }
     }
+    return end.fate;
 }
 
-// ---------------------------------------------------------------- forward: one photon per lane
+// Per-wave fate tally: ballots give wave-uniform counts, so no atomics here.
+__device__ __forceinline__ void tally_wave(uint32_t cnt[6], int fate) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        cnt[f] += (uint32_t)__builtin_amdgcn_readfirstlane((int)__popcll(__ballot(fate == f)));
+}
+
+// Fold the per-wave tallies of a block into the caller's fate counters.  The
+// block sums its waves in LDS; thread 0 adds the block total into one of
+// kTallySlots cache-line slots (so concurrent blocks contend on 16 lines, not
+// one); the last block to finish moves the slot totals into out.fate_counts
+// and leaves the slots at zero for the next launch.  Called by every thread.
+__device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs &out, const uint32_t cnt[6],
+                                            uint32_t *lds_cnt) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    if (lane == 0)
+        for (int f = 0; f < 6; ++f) lds_cnt[6 * wave + f] = cnt[f];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *slot = S.tally + (size_t)(blockIdx.x % kTallySlots) * kTallyStride;
+        for (int f = 0; f < 6; ++f) {
+            unsigned long long sum = 0;
+            for (int w = 0; w < waves; ++w) sum += lds_cnt[6 * w + f];
+            if (sum) atomicAdd(slot + f, sum);
+        }
+        __threadfence();
+        unsigned long long *fin = S.tally + (size_t)kTallySlots * kTallyStride;
+        unsigned long long done = atomicAdd(fin, 1ull);
+        if (done == (unsigned long long)gridDim.x - 1ull) {
+            __threadfence();
+            for (int f = 0; f < 6; ++f) {
+                unsigned long long tot = 0;
+                for (int k = 0; k < kTallySlots; ++k) tot += atomicExch(S.tally + (size_t)k * kTallyStride + f, 0ull);
+                if (tot) atomicAdd(out.fate_counts + f, tot);
+            }
+            atomicExch(fin, 0ull);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- forward: grid-stride over photons
 
 constexpr int kForwardBlock = 256;
+constexpr int kForwardBlocksPerCu = 8;
 
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                                 uint64_t first, uint64_t seed) {
     extern __shared__ uint32_t lds_stack[];
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+    uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        uint64_t i = base + threadIdx.x;
+        int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+        if (out.fate_counts) tally_wave(cnt, fate);
+    }
+    if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
 
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
-                          uint64_t seed, hipStream_t st) {
+                          uint64_t seed, int n_cu, hipStream_t st) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + kForwardBlock - 1) / kForwardBlock;
-    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t);
+    uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
+    if (blocks > cap) blocks = cap;
+    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + 6 * (kForwardBlock / 64) * sizeof(uint32_t);
     hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
                        seed);
     return hipGetLastError();
@@ -292,6 +335,7 @@ __global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, D
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
+    uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
     while (true) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(counter, (unsigned long long)chunk);
@@ -300,14 +344,16 @@ __global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, D
         if (base >= n) break;
         for (int k = 0; k < chunk; k += 64) {
             uint64_t g = base + (uint64_t)k + (uint64_t)lane;
-            photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+            int fate = photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+            if (out.fate_counts) tally_wave(cnt, fate);
         }
     }
+    if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
 
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, hipStream_t st) {
-    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t);
+    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t) + 6 * (block / 64) * sizeof(uint32_t);
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk);
     return hipGetLastError();
 }

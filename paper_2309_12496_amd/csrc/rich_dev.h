@@ -17,7 +17,9 @@ namespace rich {
 constexpr uint32_t kStreamTag = 0x52494348u;   // fourth Philox counter word ("RICH")
 constexpr int kStackDepth = 32;                // per-lane traversal stack entries (LDS)
 constexpr int kMaxTable = 32;
-constexpr int kMaxPath = 8;                    // surfaces recorded by the adjoint
+constexpr int kTallySlots = 16;                // fate-count slots, one 128-byte line each
+constexpr int kTallyStride = 16;               // 64-bit words per slot
+constexpr int kTallyWords = kTallySlots * kTallyStride + kTallyStride;  // slots + finisher counter line
 
 // BVH4 child reference encoding.
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;       // no child
@@ -101,11 +103,13 @@ struct alignas(16) RectDev {
     float pad;
 };
 
+// Piecewise-linear table: nodes x, values y, slope s[j] = (y[j+1]-y[j])/(x[j+1]-x[j]) (FP64 on the host).
 struct MatDev {
     int32_t kind;
     int32_t n;
     float x[kMaxTable];
     float y[kMaxTable];
+    float s[kMaxTable];
 };
 
 struct DetDev {
@@ -115,8 +119,10 @@ struct DetDev {
     float act_hu, act_hv;    // half sizes of the pixel grid
     int32_t nx, ny;
     int32_t n_qe;
+    float inv_pitch;
     float qe_x[kMaxTable];
     float qe_y[kMaxTable];
+    float qe_s[kMaxTable];
 };
 
 // FP64 master data used by the parameter update kernel.
@@ -141,6 +147,7 @@ struct DevScene {
     const Instance *inst;
     const DetDev *det;
     unsigned int *status;
+    unsigned long long *tally;   // fate-count slots (kTallyWords), zero between launches
     int32_t n_caps, n_rects, n_mats, n_inst;
     int32_t has_mesh, has_box;
     uint32_t top_root;

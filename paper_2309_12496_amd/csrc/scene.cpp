@@ -147,7 +147,8 @@ void free_scene(rich_scene *s) {
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     void *ptrs[] = {s->d_nodes, s->d_tris, s->d_inst, s->d_caps, s->d_caps_static, s->d_segs, s->d_rects,
-                    s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counter, s->d_partials};
+                    s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counter, s->d_partials,
+                    s->d_tally};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(prev);
@@ -280,6 +281,8 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
         for (int q = 0; q < m.n_refl; ++q) {
             md.x[q] = (float)m.refl_lambda[q];
             md.y[q] = (float)m.refl_value[q];
+            if (q + 1 < m.n_refl)
+                md.s[q] = (float)((m.refl_value[q + 1] - m.refl_value[q]) / (m.refl_lambda[q + 1] - m.refl_lambda[q]));
         }
     }
     std::vector<RectDev> rects(d->n_rects);
@@ -310,9 +313,12 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     det.nx = t.nx;
     det.ny = t.ny;
     det.n_qe = t.n_qe;
+    det.inv_pitch = (float)(1.0 / t.pitch);
     for (int q = 0; q < t.n_qe; ++q) {
         det.qe_x[q] = (float)t.qe_lambda[q];
         det.qe_y[q] = (float)t.qe_value[q];
+        if (q + 1 < t.n_qe)
+            det.qe_s[q] = (float)((t.qe_value[q + 1] - t.qe_value[q]) / (t.qe_lambda[q + 1] - t.qe_lambda[q]));
     }
     std::vector<SegDev> segs(d->n_segments);
     std::vector<float> params(6 * (size_t)d->n_segments);
@@ -359,9 +365,11 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     std::vector<CapDev> zero_caps(d->n_caps);
     unsigned int zero_status = 0;
     unsigned long long zero_counter = 0;
+    std::vector<unsigned long long> zero_tally(kTallyWords, 0ull);
     if ((st = upload(&s->d_caps, zero_caps.data(), zero_caps.size(), &bytes)) ||
         (st = upload(&s->d_status, &zero_status, 1, &bytes)) ||
-        (st = upload(&s->d_counter, &zero_counter, 1, &bytes))) {
+        (st = upload(&s->d_counter, &zero_counter, 1, &bytes)) ||
+        (st = upload(&s->d_tally, zero_tally.data(), zero_tally.size(), &bytes))) {
         free_scene(s);
         (void)hipSetDevice(prev);
         return st;
@@ -383,6 +391,7 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     S.inst = s->d_inst;
     S.det = s->d_det;
     S.status = s->d_status;
+    S.tally = s->d_tally;
     S.n_caps = d->n_caps;
     S.n_rects = d->n_rects;
     S.n_mats = d->n_materials;

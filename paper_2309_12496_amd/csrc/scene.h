@@ -27,6 +27,7 @@ struct rich_scene {
     float *d_params = nullptr;
     unsigned int *d_status = nullptr;
     unsigned long long *d_counter = nullptr;   // batch work counter
+    unsigned long long *d_tally = nullptr;     // fate-count slots shared by launches on this scene
     float *d_partials = nullptr;               // adjoint per-block partial sums
     size_t partials_floats = 0;
 

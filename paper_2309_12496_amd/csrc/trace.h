@@ -41,10 +41,9 @@ __device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k ==
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
-        uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        uint64_t p0 = (uint64_t)0xD2511F53u * c.x;   // one 32x32->64 multiply gives both halves
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -59,15 +58,22 @@ __device__ __forceinline__ uint4 photon_block(uint64_t seed, uint64_t g, uint32_
 // top 24 bits as a float in [0,1): exact
 __device__ __forceinline__ float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-8f; }
 
+// Hardware reciprocal (1 ulp).  Used on the geometric path where a few ulps
+// are far below the tolerance; the IEEE division sequence costs ~10 instructions.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ---------------------------------------------------------------- tables
 
-__device__ __forceinline__ float lerp_table(int n, const float *x, const float *y, float l) {
-    if (l <= x[0]) return y[0];
-    if (l >= x[n - 1]) return y[n - 1];
-    int i = 0;
-    while (i + 2 < n && l >= x[i + 1]) ++i;
-    float w = (l - x[i]) / (x[i + 1] - x[i]);
-    return fmaf(w, y[i + 1] - y[i], y[i]);
+// Piecewise-linear table with per-segment slopes, clamped outside its range.
+// The loop bound and the node addresses are uniform, so the nodes arrive
+// through scalar loads and each lane only selects.
+__device__ __forceinline__ float lerp_table(int n, const float *x, const float *y, const float *sl, float l) {
+    float v = l <= x[0] ? y[0] : y[n - 1];
+    for (int j = 0; j + 1 < n; ++j) {
+        float xa = x[j];
+        if (l >= xa && l < x[j + 1]) v = fmaf(sl[j], l - xa, y[j]);
+    }
+    return v;
 }
 
 // ---------------------------------------------------------------- generation
@@ -129,7 +135,7 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
         ct = src.cos_t;
         st = src.sin_t;
     }
-    ph.lambda = 1.0f / fmaf(-u24(w.y), src.inv_span, src.inv_lmin);
+    ph.lambda = rcp(fmaf(-u24(w.y), src.inv_span, src.inv_lmin));
     float sp, cp;
     sincospif(2.0f * u24(w.x), &sp, &cp);
     V3 d = fma3(ct, T, st * fma3(cp, E1, sp * E2));
@@ -149,7 +155,7 @@ struct Ray {
 };
 
 __device__ __forceinline__ float safe_inv(float x) {
-    return 1.0f / (fabsf(x) > 1e-30f ? x : copysignf(1e-30f, x));
+    return rcp(fabsf(x) > 1e-30f ? x : copysignf(1e-30f, x));
 }
 
 __device__ __forceinline__ void ray_setup(Ray &r, V3 o, V3 d) {
@@ -166,7 +172,7 @@ __device__ __forceinline__ void ray_setup(Ray &r, V3 o, V3 d) {
     r.kx = kx;
     r.ky = ky;
     r.kz = kz;
-    r.sz = 1.0f / dz;
+    r.sz = rcp(dz);
     r.sx = comp(d, kx) * r.sz;
     r.sy = comp(d, ky) * r.sz;
 }
@@ -211,7 +217,7 @@ __device__ __forceinline__ bool hit_cap(const CapDev &cp, V3 o, V3 d, float tmin
     float c = fmaf(-R, R, dot(f, f));
     float q = -(b + copysignf(sq, b));
     if (q == 0.0f) return false;
-    float r0 = c / q, r1 = q;
+    float r0 = c * rcp(q), r1 = q;
     float ta = fminf(r0, r1), tb = fmaxf(r0, r1);
     V3 ax = ld3(cp.axis), O = ld3(cp.O), A = ld3(cp.A), B = ld3(cp.B);
 #pragma unroll
@@ -236,7 +242,7 @@ __device__ __forceinline__ bool hit_plane_rect(V3 c, V3 n, V3 U, V3 W, float hu,
     float dn = dot(d, n);
     if (dn == 0.0f) return false;
     V3 co = c - o;
-    float t = dot(co, n) / dn;
+    float t = dot(co, n) * rcp(dn);
     if (!(t > tmin)) return false;
     V3 Pc = fma3(t, d, o - c);
     float u = dot(Pc, U), v = dot(Pc, W);
@@ -247,19 +253,13 @@ __device__ __forceinline__ bool hit_plane_rect(V3 c, V3 n, V3 U, V3 W, float hu,
     return false;
 }
 
-__device__ __forceinline__ bool hit_box(const float *lo, const float *hi, V3 o, V3 d, float tmin, float &t_out) {
-    float tn = -INFINITY, tf = INFINITY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float oa = comp(o, a), da = comp(d, a);
-        if (da == 0.0f) {
-            if (oa < lo[a] || oa > hi[a]) return false;
-            continue;
-        }
-        float t1 = (lo[a] - oa) / da, t2 = (hi[a] - oa) / da;
-        tn = fmaxf(tn, fminf(t1, t2));
-        tf = fminf(tf, fmaxf(t1, t2));
-    }
+// Box surface through the ray's inverse direction: entry or exit, whichever is first beyond tmin.
+__device__ __forceinline__ bool hit_box(const float *lo, const float *hi, const Ray &r, float tmin, float &t_out) {
+    float t0x = fmaf(lo[0], r.inv.x, -r.oi.x), t1x = fmaf(hi[0], r.inv.x, -r.oi.x);
+    float t0y = fmaf(lo[1], r.inv.y, -r.oi.y), t1y = fmaf(hi[1], r.inv.y, -r.oi.y);
+    float t0z = fmaf(lo[2], r.inv.z, -r.oi.z), t1z = fmaf(hi[2], r.inv.z, -r.oi.z);
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
     if (tn > tf) return false;
     if (tn > tmin) { t_out = tn; return true; }
     if (tf > tmin) { t_out = tf; return true; }
@@ -286,7 +286,7 @@ __device__ __forceinline__ bool hit_tri(const Ray &r, const float4 &a, const flo
     float det = U + V + W;
     if (det == 0.0f) return false;
     float T = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
-    float t = T / det;
+    float t = T * rcp(det);
     if (!(t > tmin)) return false;
     t_out = t;
     return true;
@@ -300,9 +300,9 @@ __device__ __forceinline__ void to_frame(Ray &r, const Instance &in, V3 ow, V3 d
 
 // Closest triangle along (ow, dw) with t < h.t, through the two-level BVH4.
 // stk points at this lane's first LDS stack slot; entries are `stride` apart.
-__device__ __forceinline__ void traverse(const DevScene &S, V3 ow, V3 dw, Hit &h, uint32_t *stk, int stride) {
-    Ray r;
-    ray_setup(r, ow, dw);
+__device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hit &h, uint32_t *stk, int stride) {
+    const V3 ow = world.o, dw = world.d;
+    Ray r = world;
     int inst = -1;
     int sp = 0;
     uint32_t ref = S.top_root;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void traverse(const DevScene &S, V3 ow, V3 dw, Hit &h
             continue;
         }
         if (ref == kExitMarker) {
-            ray_setup(r, ow, dw);
+            r = world;
             inst = -1;
         } else if (ref & kInstBit) {
             int k = (int)(ref & ~(kLeafBit | kInstBit));
@@ -402,19 +402,17 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det
     h.inst = -1;
     h.root = 0;
     const float tmin = S.t_min;
+    Ray r;
+    ray_setup(r, o, d);
     float t;
-    if (S.n_caps > 0) {
-        Ray r;
-        ray_setup(r, o, d);
-        for (int i = 0; i < S.n_caps; ++i) {
-            const CapDev &cp = S.caps[i];
-            if (slab_entry(r, cp.lo[0], cp.lo[1], cp.lo[2], cp.hi[0], cp.hi[1], cp.hi[2], h.t) == INFINITY) continue;
-            int root;
-            if (hit_cap(cp, o, d, tmin, t, root) && better(t, (uint32_t)i, h)) {
-                h.t = t;
-                h.prim = (uint32_t)i;
-                h.root = root;
-            }
+    for (int i = 0; i < S.n_caps; ++i) {
+        const CapDev &cp = S.caps[i];
+        if (slab_entry(r, cp.lo[0], cp.lo[1], cp.lo[2], cp.hi[0], cp.hi[1], cp.hi[2], h.t) == INFINITY) continue;
+        int root;
+        if (hit_cap(cp, o, d, tmin, t, root) && better(t, (uint32_t)i, h)) {
+            h.t = t;
+            h.prim = (uint32_t)i;
+            h.root = root;
         }
     }
     for (int i = 0; i < S.n_rects; ++i) {
@@ -430,11 +428,24 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det
         h.t = t;
         h.prim = S.prim_det;
     }
-    if (S.has_box && hit_box(S.box_lo, S.box_hi, o, d, tmin, t) && better(t, S.prim_box, h)) {
+    if (S.has_box && hit_box(S.box_lo, S.box_hi, r, tmin, t) && better(t, S.prim_box, h)) {
         h.t = t;
         h.prim = S.prim_box;
     }
-    if (S.has_mesh) traverse(S, o, d, h, stk, stride);
+    if (S.has_mesh) traverse(S, r, h, stk, stride);
+}
+
+// Reflectivity of material `mat` at `lambda`.  The loop over materials is
+// uniform so every table is read through scalar loads; lanes select their own.
+__device__ __forceinline__ float reflectivity(const DevScene &S, int mat, float lambda) {
+    float v = 0.0f;
+    for (int m = 0; m < S.n_mats; ++m) {
+        const MatDev &M = S.mats[m];
+        if (M.kind != 0) continue;
+        float r = lerp_table(M.n, M.x, M.y, M.s, lambda);
+        v = (mat == m) ? r : v;
+    }
+    return v;
 }
 
 // ---------------------------------------------------------------- interaction
@@ -458,7 +469,7 @@ __device__ __forceinline__ V3 surface_normal(const DevScene &S, const Hit &h, V3
     if (h.prim < (uint32_t)S.n_caps) {
         const CapDev &cp = S.caps[h.prim];
         mat = cp.material;
-        return (1.0f / cp.R) * (ld3(cp.C) - P);
+        return rcp(cp.R) * (ld3(cp.C) - P);
     }
     if (h.prim < S.prim_det) {
         const RectDev &rc = S.rects[h.prim - S.n_caps];
@@ -494,7 +505,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             }
             V3 Pc = fma3(h.t, d, o - ld3(det.c));
             float u = dot(Pc, ld3(det.u)), v = dot(Pc, ld3(det.v));
-            float fi = floorf((u + det.act_hu) / det.pitch), fj = floorf((v + det.act_hv) / det.pitch);
+            float fi = floorf((u + det.act_hu) * det.inv_pitch), fj = floorf((v + det.act_hv) * det.inv_pitch);
             if (!(fi >= 0.0f && fi < (float)det.nx && fj >= 0.0f && fj < (float)det.ny)) {  // NaN-safe
                 end.fate = kAbsorbed;
                 break;
@@ -504,7 +515,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             end.u = u;
             end.v = v;
             rec.detect(b, o, d, h.t);
-            float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, ph.lambda);
+            float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
             end.fate = ph.u_qe < qe ? kDetected : kQeRejected;
             break;
         }
@@ -515,8 +526,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
         V3 P = fma3(h.t, d, o);
         int mat;
         V3 n = surface_normal(S, h, P, mat);
-        const MatDev &m = S.mats[mat];
-        if (m.kind != 0 || dot(d, n) >= 0.0f) {
+        if (S.mats[mat].kind != 0 || dot(d, n) >= 0.0f) {
             end.fate = kAbsorbed;
             break;
         }
@@ -527,7 +537,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
         }
         int w = b & 3;
         uint32_t word = w == 0 ? blk.x : (w == 1 ? blk.y : (w == 2 ? blk.z : blk.w));
-        float refl = lerp_table(m.n, m.x, m.y, ph.lambda);
+        float refl = reflectivity(S, mat, ph.lambda);
         if (u24(word) >= refl) {
             end.fate = kAbsorbedMirror;
             break;
