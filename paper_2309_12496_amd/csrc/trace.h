@@ -154,6 +154,8 @@ struct Ray {
     float sx, sy, sz; // watertight shear
 };
 
+constexpr float kFarScale = 1.0000004f;
+
 __device__ __forceinline__ float safe_inv(float x) {
     return rcp(fabsf(x) > 1e-30f ? x : copysignf(1e-30f, x));
 }
@@ -178,6 +180,10 @@ __device__ __forceinline__ void ray_setup(Ray &r, V3 o, V3 d) {
 }
 
 // Slab test of an AABB with the robust far-distance scaling of Ize (JCGT 2013).
+// Returns INFINITY on a miss, else a visiting-order key: the entry distance,
+// or, when the ray starts inside the box, the exit distance (an enclosure
+// that contains the origin is then visited after the surfaces in front of it,
+// whose hits cull most of it).
 __device__ __forceinline__ float slab_entry(const Ray &r, float lx, float ly, float lz, float hx, float hy, float hz,
                                             float tmax) {
     float t0x = fmaf(lx, r.inv.x, -r.oi.x), t1x = fmaf(hx, r.inv.x, -r.oi.x);
@@ -186,7 +192,18 @@ __device__ __forceinline__ float slab_entry(const Ray &r, float lx, float ly, fl
     float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000004f;
     tf = fminf(tf, tmax);
-    return tn <= tf ? tn : INFINITY;
+    return tn <= tf ? (tn > 0.0f ? tn : tf) : INFINITY;
+}
+
+// Node-child version of slab_entry with the near and far planes already
+// chosen by the direction signs (inverted empty boxes give tn > tf: a miss).
+__device__ __forceinline__ float child_key(const Ray &r, float nx, float ny, float nz, float fx, float fy, float fz,
+                                           float tmax) {
+    float tn = fmaxf(fmaxf(fmaf(nx, r.inv.x, -r.oi.x), fmaf(ny, r.inv.y, -r.oi.y)),
+                     fmaxf(fmaf(nz, r.inv.z, -r.oi.z), 0.0f));
+    float tf = fminf(fminf(fmaf(fx, r.inv.x, -r.oi.x), fmaf(fy, r.inv.y, -r.oi.y)), fmaf(fz, r.inv.z, -r.oi.z));
+    tf = fminf(tf * kFarScale, tmax);
+    return tn <= tf ? (tn > 0.0f ? tn : tf) : INFINITY;
 }
 
 // ---------------------------------------------------------------- closest hit
@@ -292,10 +309,10 @@ __device__ __forceinline__ bool hit_tri(const Ray &r, const float4 &a, const flo
     return true;
 }
 
-__device__ __forceinline__ void to_frame(Ray &r, const Instance &in, V3 ow, V3 dw) {
-    V3 o = mat3(in.m, ow - ld3(in.org));
-    V3 d = mat3(in.m, dw);
-    ray_setup(r, o, d);
+// Re-origin the ray at o (same direction): only the origin terms change.
+__device__ __forceinline__ void set_origin(Ray &r, V3 o) {
+    r.o = o;
+    r.oi = V3{o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z};
 }
 
 // Closest triangle along (ow, dw) with t < h.t, through the two-level BVH4.
@@ -304,24 +321,24 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
     const V3 ow = world.o, dw = world.d;
     Ray r = world;
     int inst = -1;
+    bool moved = false;   // current frame rotated/scaled (a parametrised segment)
     int sp = 0;
     uint32_t ref = S.top_root;
     const float tmin = S.t_min;
     while (true) {
         if (!(ref & kLeafBit)) {
             const Node4 &nd = S.nodes[ref];
-            float4 lx = *reinterpret_cast<const float4 *>(nd.lox);
-            float4 hx = *reinterpret_cast<const float4 *>(nd.hix);
-            float4 ly = *reinterpret_cast<const float4 *>(nd.loy);
-            float4 hy = *reinterpret_cast<const float4 *>(nd.hiy);
-            float4 lz = *reinterpret_cast<const float4 *>(nd.loz);
-            float4 hz = *reinterpret_cast<const float4 *>(nd.hiz);
+            // near and far planes per axis follow the sign of the direction
+            const float4 *pl = reinterpret_cast<const float4 *>(nd.lox);
+            float4 nx = pl[r.inv.x >= 0.0f ? 0 : 1], fx = pl[r.inv.x >= 0.0f ? 1 : 0];
+            float4 ny = pl[r.inv.y >= 0.0f ? 2 : 3], fy = pl[r.inv.y >= 0.0f ? 3 : 2];
+            float4 nz = pl[r.inv.z >= 0.0f ? 4 : 5], fz = pl[r.inv.z >= 0.0f ? 5 : 4];
             uint4 ch = *reinterpret_cast<const uint4 *>(nd.child);
-            float tmax = h.t;
-            float d0 = slab_entry(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmax);
-            float d1 = slab_entry(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmax);
-            float d2 = slab_entry(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmax);
-            float d3 = slab_entry(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmax);
+            const float tmax = h.t;
+            float d0 = child_key(r, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmax);
+            float d1 = child_key(r, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tmax);
+            float d2 = child_key(r, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tmax);
+            float d3 = child_key(r, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tmax);
             uint32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
             // empty slots have inverted boxes, which a min/max slab test would accept
             if (c0 == kEmpty) d0 = INFINITY;
@@ -357,8 +374,10 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             continue;
         }
         if (ref == kExitMarker) {
-            r = world;
+            if (moved) ray_setup(r, ow, dw);
+            else set_origin(r, ow);
             inst = -1;
+            moved = false;
         } else if (ref & kInstBit) {
             int k = (int)(ref & ~(kLeafBit | kInstBit));
             if (sp + 1 > kStackDepth) {
@@ -366,7 +385,12 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             } else {
                 stk[(sp++) * stride] = kExitMarker;
                 const Instance &in = S.inst[k];
-                to_frame(r, in, ow, dw);
+                if (in.segment < 0) {
+                    set_origin(r, ow - ld3(in.org));   // fixed instances only translate
+                } else {
+                    ray_setup(r, mat3(in.m, ow - ld3(in.org)), mat3(in.m, dw));
+                    moved = true;
+                }
                 inst = k;
                 ref = in.root;
                 continue;
