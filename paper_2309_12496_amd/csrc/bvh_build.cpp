@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <map>
+#include <tuple>
 
 namespace rich {
 
@@ -68,6 +70,59 @@ struct Builder {
             for (int a = 0; a < 3; ++a) cen[3 * i + a] = 0.5 * (b.lo[a] + b.hi[a]);
             idx[i] = (uint32_t)i;
         }
+    }
+
+    // Planar grouping: a mesh made of a few planes (an enclosure's walls) gets
+    // one subtree per plane, the planes chained under the root so that the
+    // BVH4 root holds thin per-wall boxes rather than half-box boxes that
+    // contain every ray starting inside.  Returns the root, or -1 if the mesh
+    // is not a union of 2..64 planes.
+    int build_planar() {
+        size_t n = tris.size();
+        std::map<std::tuple<long long, long long, long long, long long>, int> key_to_group;
+        std::vector<int> grp(n);
+        for (size_t i = 0; i < n; ++i) {
+            const BuildTri &t = tris[i];
+            double off = t.n[0] * t.v[0][0] + t.n[1] * t.v[0][1] + t.n[2] * t.v[0][2];
+            auto key = std::make_tuple(std::llround(t.n[0] * 1e6), std::llround(t.n[1] * 1e6), std::llround(t.n[2] * 1e6),
+                                       std::llround(off * 1e3));
+            auto it = key_to_group.find(key);
+            if (it == key_to_group.end()) {
+                if (key_to_group.size() >= 64) return -1;
+                it = key_to_group.emplace(key, (int)key_to_group.size()).first;
+            }
+            grp[i] = it->second;
+        }
+        int ng = (int)key_to_group.size();
+        if (ng < 2) return -1;
+        std::vector<uint32_t> gcount(ng, 0);
+        for (int g : grp) ++gcount[g];
+        // groups by decreasing size, triangles contiguous per group
+        std::vector<int> order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return gcount[a] > gcount[b] || (gcount[a] == gcount[b] && a < b); });
+        std::vector<int> rank(ng);
+        for (int r = 0; r < ng; ++r) rank[order[r]] = r;
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return rank[grp[a]] < rank[grp[b]]; });
+        std::vector<uint32_t> start(ng + 1, 0);
+        for (int r = 0; r < ng; ++r) start[r + 1] = start[r] + gcount[order[r]];
+        return chain(0, ng, start);
+    }
+
+    int chain(int r, int ng, const std::vector<uint32_t> &start) {
+        if (r == ng - 1) return build(start[r], start[r + 1] - start[r]);
+        int me = (int)bn.size();
+        bn.emplace_back();
+        int l = build(start[r], start[r + 1] - start[r]);
+        int rt = chain(r + 1, ng, start);
+        BuildBox box = bn[l].box;
+        grow(box, bn[rt].box);
+        bn[me].box = box;
+        bn[me].first = start[r];
+        bn[me].count = start[ng] - start[r];
+        bn[me].left = l;
+        bn[me].right = rt;
+        return me;
     }
 
     int build(uint32_t first, uint32_t count) {
@@ -252,10 +307,11 @@ uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes,
                          BuildBox *bounds) {
     Builder b(tris);
     b.bn.reserve(2 * tris.size() / kLeafSize + 2);
-    b.build(0, (uint32_t)tris.size());
-    if (bounds) *bounds = b.bn[0].box;
+    int top = b.build_planar();
+    if (top < 0) top = b.build(0, (uint32_t)tris.size());
+    if (bounds) *bounds = b.bn[top].box;
     Emitter e{b.bn, b.idx, tris, nodes, out};
-    uint32_t root = e.emit(0, 1);
+    uint32_t root = e.emit(top, 1);
     if (depth) *depth = e.max_depth;
     return root;
 }
