@@ -327,50 +327,51 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
     const float tmin = S.t_min;
     while (true) {
         if (!(ref & kLeafBit)) {
-            const Node4 &nd = S.nodes[ref];
-            // near and far planes per axis follow the sign of the direction
-            const float4 *pl = reinterpret_cast<const float4 *>(nd.lox);
-            float4 nx = pl[r.inv.x >= 0.0f ? 0 : 1], fx = pl[r.inv.x >= 0.0f ? 1 : 0];
-            float4 ny = pl[r.inv.y >= 0.0f ? 2 : 3], fy = pl[r.inv.y >= 0.0f ? 3 : 2];
-            float4 nz = pl[r.inv.z >= 0.0f ? 4 : 5], fz = pl[r.inv.z >= 0.0f ? 5 : 4];
-            uint4 ch = *reinterpret_cast<const uint4 *>(nd.child);
+            // near/far planes per axis follow the direction signs; 32-bit byte
+            // offsets from the uniform base keep the address arithmetic scalar
+            const char *nb = reinterpret_cast<const char *>(S.nodes);
+            const uint32_t off = ref << 7;
+            const float4 nx = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.x >= 0.0f ? 0u : 16u)));
+            const float4 fx = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.x >= 0.0f ? 16u : 0u)));
+            const float4 ny = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.y >= 0.0f ? 32u : 48u)));
+            const float4 fy = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.y >= 0.0f ? 48u : 32u)));
+            const float4 nz = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.z >= 0.0f ? 64u : 80u)));
+            const float4 fz = *reinterpret_cast<const float4 *>(nb + (off + (r.inv.z >= 0.0f ? 80u : 64u)));
+            const uint4 ch = *reinterpret_cast<const uint4 *>(nb + (off + 96u));
             const float tmax = h.t;
-            float d0 = child_key(r, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmax);
-            float d1 = child_key(r, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tmax);
-            float d2 = child_key(r, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tmax);
-            float d3 = child_key(r, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tmax);
-            uint32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-            // empty slots have inverted boxes, which a min/max slab test would accept
-            if (c0 == kEmpty) d0 = INFINITY;
-            if (c1 == kEmpty) d1 = INFINITY;
-            if (c2 == kEmpty) d2 = INFINITY;
-            if (c3 == kEmpty) d3 = INFINITY;
-            // sort the four (distance, child) pairs ascending: 5 compare-exchanges
-#define RICH_CX(da, ca, db, cb)                                  \
-    if (db < da) {                                               \
-        float tf_ = da; da = db; db = tf_;                       \
-        uint32_t tc_ = ca; ca = cb; cb = tc_;                    \
-    }
-            RICH_CX(d0, c0, d1, c1);
-            RICH_CX(d2, c2, d3, c3);
-            RICH_CX(d0, c0, d2, c2);
-            RICH_CX(d1, c1, d3, c3);
-            RICH_CX(d1, c1, d2, c2);
-#undef RICH_CX
-            if (d0 == INFINITY) {
+            // keys: distance bits with the child slot in the two lowest mantissa bits
+            // (non-negative floats order like unsigned integers; a miss is +inf)
+            uint32_t k0 = (__float_as_uint(child_key(r, nx.x, ny.x, nz.x, fx.x, fy.x, fz.x, tmax)) & ~3u) | 0u;
+            uint32_t k1 = (__float_as_uint(child_key(r, nx.y, ny.y, nz.y, fx.y, fy.y, fz.y, tmax)) & ~3u) | 1u;
+            uint32_t k2 = (__float_as_uint(child_key(r, nx.z, ny.z, nz.z, fx.z, fy.z, fz.z, tmax)) & ~3u) | 2u;
+            uint32_t k3 = (__float_as_uint(child_key(r, nx.w, ny.w, nz.w, fx.w, fy.w, fz.w, tmax)) & ~3u) | 3u;
+            // 4-element sorting network, branch-free
+            uint32_t t;
+            t = min(k0, k1); k1 = max(k0, k1); k0 = t;
+            t = min(k2, k3); k3 = max(k2, k3); k2 = t;
+            t = min(k0, k2); k2 = max(k0, k2); k0 = t;
+            t = min(k1, k3); k3 = max(k1, k3); k1 = t;
+            t = min(k1, k2); k2 = max(k1, k2); k1 = t;
+            const uint32_t kMiss = 0x7F800000u;   // +inf
+            if (k0 >= kMiss) {
                 if (sp == 0) break;
                 ref = stk[(--sp) * stride];
                 continue;
             }
-            int need = (d1 != INFINITY) + (d2 != INFINITY) + (d3 != INFINITY);
+            // children of empty slots never pass the slab test (inverted boxes)
+            auto pick = [&](uint32_t k) -> uint32_t {
+                uint32_t j = k & 3u;
+                return j == 0 ? ch.x : (j == 1 ? ch.y : (j == 2 ? ch.z : ch.w));
+            };
+            int need = (k1 < kMiss) + (k2 < kMiss) + (k3 < kMiss);
             if (sp + need > kStackDepth) {
                 atomicOr(S.status, 2u);  // RICH_FLAG_STACK_OVERFLOW
                 need = kStackDepth - sp;
             }
-            if (need >= 3) stk[(sp++) * stride] = c3;
-            if (need >= 2) stk[(sp++) * stride] = c2;
-            if (need >= 1) stk[(sp++) * stride] = c1;
-            ref = c0;
+            if (need >= 3) stk[(sp++) * stride] = pick(k3);
+            if (need >= 2) stk[(sp++) * stride] = pick(k2);
+            if (need >= 1) stk[(sp++) * stride] = pick(k1);
+            ref = pick(k0);
             continue;
         }
         if (ref == kExitMarker) {
@@ -399,8 +400,10 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             uint32_t first = ref & 0x07FFFFFFu;
             uint32_t cnt = ((ref >> 27) & 7u) + 1u;
             for (uint32_t q = first; q < first + cnt; ++q) {
-                const float4 *tp = reinterpret_cast<const float4 *>(S.tris + q);
-                float4 a = tp[0], b = tp[1], c = tp[2];
+                const char *tb = reinterpret_cast<const char *>(S.tris) + (q << 6);
+                float4 a = *reinterpret_cast<const float4 *>(tb);
+                float4 b = *reinterpret_cast<const float4 *>(tb + 16);
+                float4 c = *reinterpret_cast<const float4 *>(tb + 32);
                 float t;
                 if (hit_tri(r, a, b, c, tmin, t)) {
                     uint32_t prim = S.prim_tri + __float_as_uint(a.w);
