@@ -33,14 +33,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# Algorithmic VALU work per photon of forward_kernel on the headline workload,
-# in lane operations (SQ_INSTS_VALU x 64 / photons, see profiles/).  None until measured.
-ALU_OPS_PER_PHOTON = None
+# VALU work per photon of forward_kernel on the headline workload, in 32-bit
+# lane operations: SQ_INSTS_VALU x 64 lanes / photons = 1.1273e9 x 64 / 1e7
+# (profiles/forward_kernel_c2_counters.md).  Issued slots, inactive lanes included.
+ALU_OPS_PER_PHOTON = 7214.6
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 (writes).
 OUT_BYTES_PER_PHOTON = 25.0
-# HBM bytes per photon counted by FETCH_SIZE + WRITE_SIZE for the headline launch
-# (scaled by the copy-kernel calibration, see profiles/); None until measured.
-TRAFFIC_BYTES_PER_PHOTON = None
+# HBM bytes per photon of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
+# KiB per dispatch, scaled by the 256 MiB copy-kernel calibration, / 1e7 photons.
+TRAFFIC_BYTES_PER_PHOTON = (613.59 * 1.9998 + 278293.8) * 1024 / 1e7
 
 
 def parse():
@@ -192,7 +193,7 @@ def main():
     if ALU_OPS_PER_PHOTON:
         achieved = ALU_OPS_PER_PHOTON * n / (ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+                "unit": "TOP/s", "frac": achieved / VALU_PEAK_LANE_OPS,
                 "traffic": None if TRAFFIC_BYTES_PER_PHOTON is None else TRAFFIC_BYTES_PER_PHOTON * n}
     else:
         gbs = OUT_BYTES_PER_PHOTON * n / (ms * 1e-3) / 1e9
