@@ -98,7 +98,7 @@ def cpu_baseline(cfg, target_seconds):
     t0 = time.perf_counter()
     res = O.propagate(sc, cfg["source"], n, cfg["seed"], threads=threads)
     dt = time.perf_counter() - t0
-    assert int(np.bincount(res["fate"], minlength=6).sum()) == n
+    assert int(np.bincount(res["fate"], minlength=7).sum()) == n
     return {"value": n / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
             "sample": f"photon ids 0..{n - 1} of the headline workload ({dt:.1f} s on {threads} threads)"}
 

@@ -28,9 +28,10 @@
  *     (hit-list or traversal-stack overflow) are read by rich_get_status.
  *   - NULL output pointers mean "do not write".  The histogram, fate counts
  *     and hit-list counter accumulate: the caller zeroes them.
- *   - A call on a stream that another thread uses concurrently with the same
- *     scene is the caller's business; calls on one scene from one stream are
- *     ordered.
+ *   - Launches on one scene share small device counters (the batch work
+ *     counter, the fate-count slots, the adjoint partial sums), so work on
+ *     one scene must not run concurrently on two streams.  Calls on one
+ *     scene from one stream are ordered.
  */
 #ifndef RICH_H
 #define RICH_H
@@ -58,7 +59,8 @@ typedef int32_t rich_status;
 #define RICH_ABSORBED        3   /* absorber, back face, or detector dead border */
 #define RICH_ESCAPED         4   /* left the scene without hitting anything */
 #define RICH_MAX_BOUNCES     5   /* still flying after max_bounces surfaces */
-#define RICH_N_FATES         6
+#define RICH_PREFILTERED     6   /* rejected by the pre-propagation efficiency filter */
+#define RICH_N_FATES         7
 
 /* Device status flags returned by rich_get_status. */
 #define RICH_FLAG_HITLIST_OVERFLOW 0x1u
@@ -166,6 +168,21 @@ typedef struct rich_scene_stats {
 
 /* --------------------------------------------------------------- sources ---- */
 
+/* Optional pre-propagation efficiency filter, as the paper's Section 4.3
+ * applies it: each photon is kept with probability
+ *     QE(lambda) * refl_{materials[0]}(lambda) * ... * refl_{materials[n-1]}(lambda)
+ * (one factor per mirror the photons are expected to meet; Section 4.3 uses
+ * two), drawn from word 0 of Philox block 0x7FFFFFFF of the photon.  Rejected
+ * photons get fate RICH_PREFILTERED and are not traced; kept photons are
+ * traced with every efficiency equal to one (no roulette on mirrors or the
+ * detector).  enabled = 0 (the default) traces every photon with the
+ * efficiencies applied at the surfaces. */
+typedef struct rich_prefilter {
+    int32_t enabled;
+    int32_t n_materials;          /* 0..4 */
+    int32_t materials[4];         /* mirror materials whose reflectivity enters the product */
+} rich_prefilter;
+
 #define RICH_SRC_TRACK    0       /* Cherenkov photons from a straight track segment (length 0: a point) */
 #define RICH_SRC_EXPLICIT 2       /* photons given one by one (Section 4.2) */
 
@@ -181,6 +198,7 @@ typedef struct rich_source {
     const float *dev_lambda;      /* [N] nm */
     /* spectrum and radiator (TRACK) */
     double n_radiator, lambda_min, lambda_max;
+    rich_prefilter prefilter;
 } rich_source;
 
 /* One track of a batch (32 bytes). */
@@ -199,6 +217,7 @@ typedef struct rich_batch {
     int32_t n_tracks;
     int32_t reserved;
     double n_radiator, lambda_min, lambda_max;
+    rich_prefilter prefilter;
 } rich_batch;
 
 /* --------------------------------------------------------------- outputs ---- */

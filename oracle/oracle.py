@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborcl.so")
 MAX_TABLE = 32
 
-DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES = range(6)
+DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES, PREFILTERED = range(7)
+N_FATES = 7
 SRC_TRACK, SRC_BATCH, SRC_EXPLICIT = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -52,6 +53,7 @@ class Source(C.Structure):
         ("n_tracks", C.c_int64), ("tracks", _dp), ("offsets", C.POINTER(C.c_uint64)),
         ("ex_o", _dp), ("ex_d", _dp), ("ex_lambda", _dp),
         ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+        ("prefilter", C.c_int32), ("pf_n", C.c_int32), ("pf_mats", C.c_int32 * 4),
     ]
 
 
@@ -232,6 +234,12 @@ def _source(src, keep):
     s.n_radiator = float(src.get("n_radiator", 1.0))
     s.lambda_min = float(src.get("lambda_min", 200.0))
     s.lambda_max = float(src.get("lambda_max", 600.0))
+    pf = src.get("prefilter")
+    if pf is not None:
+        s.prefilter = 1
+        s.pf_n = len(pf)
+        for k, m in enumerate(pf):
+            s.pf_mats[k] = int(m)
     if kind == "track":
         s.kind = SRC_TRACK
         s.origin[:] = list(src["origin"])
@@ -330,7 +338,7 @@ def histogram(res, nx, ny):
 
 
 def fate_counts(res):
-    return np.bincount(res["fate"], minlength=6).astype(np.uint64)
+    return np.bincount(res["fate"], minlength=N_FATES).astype(np.uint64)
 
 
 def mse_loss_and_grad(res, targets, mask, n_seg):

@@ -574,6 +574,25 @@ static void onb(v3 n, v3 *b1, v3 *b2)
 
 typedef struct { v3 o, d; double lambda; double u_qe; } photon;
 
+#define PREFILTER_BLOCK 0x7FFFFFFFu
+
+/* Section 4.3: one accept-reject per photon with probability
+ * QE(lambda) * product of the listed mirrors' reflectivities. */
+static int prefilter_keep(const orc_scene *s, const orc_source *src, uint64_t seed, uint64_t g, double lambda,
+                          double *margin)
+{
+    double p = table(s->d.n_qe, s->d.qe_x, s->d.qe_y, lambda);
+    for (int k = 0; k < src->pf_n; ++k) {
+        int m = src->pf_mats[k];
+        p *= table(s->mat_nrefl[m], s->mat_refl_x + ORC_MAX_TABLE * m, s->mat_refl_y + ORC_MAX_TABLE * m, lambda);
+    }
+    uint32_t w[4];
+    photon_block(seed, g, PREFILTER_BLOCK, w);
+    double u = u24(w[0]);
+    *margin = fabs(u - p);
+    return u < p;
+}
+
 static int find_track(const orc_source *src, uint64_t g)
 {
     /* last k with offsets[k] <= g */
@@ -820,8 +839,19 @@ static void trace_photon(const job *jb, uint64_t i)
     int npath = 0;
     uint32_t blk[4];
     int have_blk = -1;
+    int eff = 1;                    /* efficiencies applied at the surfaces */
+    int nloop = s->d.max_bounces;
+    if (jb->src->prefilter) {
+        double m;
+        if (!prefilter_keep(s, jb->src, jb->seed, g, ph.lambda, &m)) {
+            fate = ORC_PREFILTERED;
+            nloop = 0;
+        }
+        rmargin = m;
+        eff = 0;
+    }
 
-    for (int b = 0; b < s->d.max_bounces; ++b) {
+    for (int b = 0; b < nloop; ++b) {
         hitrec h;
         closest_hit(s, o, d, jb->use_bvh, &h);
         if (h.prim < 0) { fate = ORC_ESCAPED; break; }
@@ -841,9 +871,13 @@ static void trace_photon(const job *jb, uint64_t i)
             pixel = (int)fj * s->d.det_nx + (int)fi;
             hxyz[0] = P.x; hxyz[1] = P.y; hxyz[2] = P.z;
             huv[0] = u; huv[1] = v;
-            double qe = table(s->d.n_qe, s->d.qe_x, s->d.qe_y, ph.lambda);
-            rmargin = mind(rmargin, fabs(ph.u_qe - qe));
-            fate = (ph.u_qe < qe) ? ORC_DETECTED : ORC_QE_REJECTED;
+            if (eff) {
+                double qe = table(s->d.n_qe, s->d.qe_x, s->d.qe_y, ph.lambda);
+                rmargin = mind(rmargin, fabs(ph.u_qe - qe));
+                fate = (ph.u_qe < qe) ? ORC_DETECTED : ORC_QE_REJECTED;
+            } else {
+                fate = ORC_DETECTED;
+            }
             break;
         }
         if (h.prim == box_id) { fate = ORC_ABSORBED; break; }
@@ -880,12 +914,14 @@ static void trace_photon(const job *jb, uint64_t i)
         }
         if (s->mat_kind[mat] != ORC_MIRROR || vdot(d, n) >= 0) { fate = ORC_ABSORBED; break; }
         /* reflectivity roulette: word (b mod 4) of block 1 + b/4 */
-        if (have_blk != 1 + b / 4) { photon_block(jb->seed, g, (uint32_t)(1 + b / 4), blk); have_blk = 1 + b / 4; }
-        double uR = u24(blk[b % 4]);
-        double R = table(s->mat_nrefl[mat], s->mat_refl_x + ORC_MAX_TABLE * mat, s->mat_refl_y + ORC_MAX_TABLE * mat,
-                         ph.lambda);
-        rmargin = mind(rmargin, fabs(uR - R));
-        if (uR >= R) { fate = ORC_ABSORBED_MIRROR; break; }
+        if (eff) {
+            if (have_blk != 1 + b / 4) { photon_block(jb->seed, g, (uint32_t)(1 + b / 4), blk); have_blk = 1 + b / 4; }
+            double uR = u24(blk[b % 4]);
+            double R = table(s->mat_nrefl[mat], s->mat_refl_x + ORC_MAX_TABLE * mat,
+                             s->mat_refl_y + ORC_MAX_TABLE * mat, ph.lambda);
+            rmargin = mind(rmargin, fabs(uR - R));
+            if (uR >= R) { fate = ORC_ABSORBED_MIRROR; break; }
+        }
         d = vsub(d, vmul(n, 2.0 * vdot(d, n)));
         o = P;
     }
@@ -923,6 +959,14 @@ static int propagate_any(const orc_scene *s, const orc_source *src, const uint64
 {
     if (!s || !src || !out) { set_err("null argument"); return -1; }
     if (ids && src->kind == ORC_SRC_EXPLICIT) { set_err("id lists need a generated source"); return -1; }
+    if (src->prefilter) {
+        if (src->pf_n < 0 || src->pf_n > 4) { set_err("prefilter: 0..4 materials"); return -1; }
+        for (int k = 0; k < src->pf_n; ++k)
+            if (src->pf_mats[k] < 0 || src->pf_mats[k] >= s->d.n_mat || s->mat_kind[src->pf_mats[k]] != ORC_MIRROR) {
+                set_err("prefilter material is not a mirror");
+                return -1;
+            }
+    }
     if (src->kind != ORC_SRC_EXPLICIT) {
         if (!(src->n_radiator > 0) || !(src->lambda_min > 0) || !(src->lambda_max > src->lambda_min)) {
             set_err("bad source spectrum");

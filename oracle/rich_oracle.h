@@ -33,7 +33,7 @@ extern "C" {
 #define ORC_MAX_TABLE 32
 
 enum { ORC_DETECTED = 0, ORC_QE_REJECTED = 1, ORC_ABSORBED_MIRROR = 2,
-       ORC_ABSORBED = 3, ORC_ESCAPED = 4, ORC_MAX_BOUNCES = 5 };
+       ORC_ABSORBED = 3, ORC_ESCAPED = 4, ORC_MAX_BOUNCES = 5, ORC_PREFILTERED = 6 };
 enum { ORC_MIRROR = 0, ORC_ABSORBER = 1 };
 enum { ORC_SRC_TRACK = 0, ORC_SRC_BATCH = 1, ORC_SRC_EXPLICIT = 2 };
 
@@ -86,6 +86,8 @@ typedef struct {
     const double *ex_o, *ex_d, *ex_lambda;
     /* common */
     double n_radiator, lambda_min, lambda_max;
+    /* pre-propagation filter (Section 4.3): keep with probability QE * prod refl(mats) */
+    int32_t prefilter, pf_n, pf_mats[4];
 } orc_source;
 
 typedef struct orc_scene orc_scene;

@@ -149,7 +149,13 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
         if (act) {
             uint64_t g = first + i;
             Photon ph = make_photon(src, seed, g, i);
-            propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec);
+            if (!src.prefilter) {
+                propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec);
+            } else if (prefilter_keep(S, det, src, ph, seed, g)) {
+                propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec, false);
+            } else {
+                end.fate = kPrefiltered;
+            }
             act = rec.hit_det && (end.fate == kDetected || end.fate == kQeRejected);
             if (act && rec.overflow) {
                 atomicOr(S.status, 4u);  // RICH_FLAG_PATH_OVERFLOW
@@ -241,21 +247,37 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
     }
 }
 
-// Sum the block partials in block order; fused-loss mode divides by the count.
-__global__ void adjoint_reduce_kernel(const float *partials, int n_blocks, int n_par, int fused, float *grad,
-                                      float *loss) {
-    extern __shared__ float sums[];
-    const int width = n_par + 2;
-    for (int j = threadIdx.x; j < width; j += blockDim.x) {
-        float s = 0.0f;
-        for (int b = 0; b < n_blocks; ++b) s += partials[(size_t)b * width + j];
-        sums[j] = s;
-    }
+// Fixed-order sum of column j of the block partials: thread t adds blocks
+// t, t+256, ... in order, then an LDS tree of fixed shape combines the threads.
+__device__ __forceinline__ float column_sum(const float *partials, int n_blocks, int width, int j, float *red) {
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) s += partials[(size_t)b * width + j];
+    red[threadIdx.x] = s;
     __syncthreads();
-    float cnt = sums[n_par + 1];
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    float v = red[0];
+    __syncthreads();
+    return v;
+}
+
+// One block per output: gradient entries 0..n_par-1 and the loss (n_par).
+// Every block recomputes the photon count the same way; fused-loss mode
+// divides by it.
+__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float *partials, int n_blocks, int n_par,
+                                                             int fused, float *grad, float *loss) {
+    __shared__ float red[256];
+    const int width = n_par + 2;
+    const int j = blockIdx.x;
+    float v = column_sum(partials, n_blocks, width, j, red);
+    float cnt = column_sum(partials, n_blocks, width, n_par + 1, red);
     float scale = fused ? (cnt > 0.0f ? 1.0f / cnt : 0.0f) : 1.0f;
-    for (int j = threadIdx.x; j < n_par; j += blockDim.x) grad[j] = sums[j] * scale;
-    if (threadIdx.x == 0 && loss) *loss = sums[n_par] * scale;
+    if (threadIdx.x == 0) {
+        if (j < n_par) grad[j] = v * scale;
+        else if (loss) *loss = v * scale;
+    }
 }
 
 int adjoint_block_size() { return kAdjBlock; }
@@ -267,8 +289,8 @@ hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const Adjoint
     hipLaunchKernelGGL(adjoint_kernel, dim3(n_blocks), dim3(kAdjBlock), lds, st, S, src, a, n, first, seed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(256), (size_t)(a.n_par + 2) * sizeof(float), st,
-                       (const float *)a.partials, n_blocks, a.n_par, a.targets ? 1 : 0, a.grad, a.loss);
+    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(a.n_par + 1), dim3(256), 0, st, (const float *)a.partials, n_blocks,
+                       a.n_par, a.targets ? 1 : 0, a.grad, a.loss);
     return hipGetLastError();
 }
 

@@ -94,6 +94,21 @@ rich_status make_track_source(const rich_source *src, DevSource &ds) {
     return RICH_OK;
 }
 
+rich_status set_prefilter(const rich_scene *s, const rich_prefilter &pf, DevSource &ds) {
+    ds.prefilter = pf.enabled ? 1 : 0;
+    ds.pf_n = 0;
+    if (!pf.enabled) return RICH_OK;
+    if (pf.n_materials < 0 || pf.n_materials > 4) return set_error(RICH_EINVAL, "prefilter: 0..4 materials");
+    for (int k = 0; k < pf.n_materials; ++k) {
+        int m = pf.materials[k];
+        if (m < 0 || m >= s->dev.n_mats || s->mat_kind[m] != RICH_MAT_MIRROR)
+            return set_error(RICH_EINVAL, "prefilter: material %d is not a mirror of this scene", m);
+        ds.pf_mats[k] = m;
+    }
+    ds.pf_n = pf.n_materials;
+    return RICH_OK;
+}
+
 rich_status make_batch_source(const rich_batch *b, DevSource &ds) {
     std::memset(&ds, 0, sizeof ds);
     if (!b->dev_tracks || !b->dev_offsets || b->n_tracks < 1)
@@ -339,6 +354,7 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
     if (st) return st;
     DevSource ds;
     if ((st = make_track_source(src, ds))) return st;
+    if ((st = set_prefilter(s, src->prefilter, ds))) return st;
     if (n_photons == 0) return RICH_OK;
     DeviceGuard g(s->device);
     RICH_HIP(launch_forward(s->dev, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
@@ -351,6 +367,7 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
     DevSource ds;
     rich_status st = make_batch_source(batch, ds);
     if (st) return st;
+    if ((st = set_prefilter(s, batch->prefilter, ds))) return st;
     DeviceGuard g(s->device);
     try {
         return run_autotune(s, ds, n_photons, seed, out);
@@ -367,6 +384,7 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
     if (st) return st;
     DevSource ds;
     if ((st = make_batch_source(batch, ds))) return st;
+    if ((st = set_prefilter(s, batch->prefilter, ds))) return st;
     if (n_photons == 0) return RICH_OK;
     DeviceGuard g(s->device);
     try {
@@ -397,7 +415,9 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
                       dout.hit_list, (void *)dout.hit_count, (unsigned long long)dout.hit_capacity, t.block, t.chunk,
                       t.blocks_per_cu);
         std::string k2 = std::string(key) + "/" + std::to_string(batch->n_radiator) + "/" +
-                         std::to_string(batch->lambda_min) + "/" + std::to_string(batch->lambda_max);
+                         std::to_string(batch->lambda_min) + "/" + std::to_string(batch->lambda_max) + "/pf" +
+                         std::to_string(ds.prefilter) + ":" + std::to_string(ds.pf_n);
+        for (int k = 0; k < ds.pf_n; ++k) k2 += "," + std::to_string(ds.pf_mats[k]);
         if (!s->graph_exec || s->graph_key != k2) {
             if (s->graph_exec) {
                 (void)hipGraphExecDestroy(s->graph_exec);
@@ -444,6 +464,7 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
     DevSource ds;
     rich_status st = src ? make_track_source(src, ds) : make_batch_source(batch, ds);
     if (st) return st;
+    if ((st = set_prefilter(s, src ? src->prefilter : batch->prefilter, ds))) return st;
     if (batch && first_photon_id != 0) return set_error(RICH_EINVAL, "batch photons start at id 0");
     DeviceGuard g(s->device);
     int n_par = 6 * s->n_segments;

@@ -210,7 +210,13 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
     if (active) {
         Photon ph = make_photon(src, seed, g, i);
         NoRecord rec;
-        propagate(S, *S.det, ph, seed, g, stk, stride, end, rec);
+        if (!src.prefilter) {
+            propagate(S, *S.det, ph, seed, g, stk, stride, end, rec);
+        } else if (prefilter_keep(S, *S.det, src, ph, seed, g)) {
+            propagate(S, *S.det, ph, seed, g, stk, stride, end, rec, false);
+        } else {
+            end.fate = kPrefiltered;
+        }
         bool on_det = end.fate == kDetected || end.fate == kQeRejected;
         if (out.fate) out.fate[i] = (uint8_t)end.fate;
         if (out.pixel) out.pixel[i] = on_det ? end.pixel : -1;
@@ -256,9 +262,9 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
 }
 
 // Per-wave fate tally: ballots give wave-uniform counts, so no atomics here.
-__device__ __forceinline__ void tally_wave(uint32_t cnt[6], int fate) {
+__device__ __forceinline__ void tally_wave(uint32_t cnt[kFates], int fate) {
 #pragma unroll
-    for (int f = 0; f < 6; ++f)
+    for (int f = 0; f < kFates; ++f)
         cnt[f] += (uint32_t)__builtin_amdgcn_readfirstlane((int)__popcll(__ballot(fate == f)));
 }
 
@@ -267,17 +273,17 @@ __device__ __forceinline__ void tally_wave(uint32_t cnt[6], int fate) {
 // kTallySlots cache-line slots (so concurrent blocks contend on 16 lines, not
 // one); the last block to finish moves the slot totals into out.fate_counts
 // and leaves the slots at zero for the next launch.  Called by every thread.
-__device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs &out, const uint32_t cnt[6],
+__device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs &out, const uint32_t cnt[kFates],
                                             uint32_t *lds_cnt) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
     if (lane == 0)
-        for (int f = 0; f < 6; ++f) lds_cnt[6 * wave + f] = cnt[f];
+        for (int f = 0; f < kFates; ++f) lds_cnt[kFates * wave + f] = cnt[f];
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long *slot = S.tally + (size_t)(blockIdx.x % kTallySlots) * kTallyStride;
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 0; f < kFates; ++f) {
             unsigned long long sum = 0;
-            for (int w = 0; w < waves; ++w) sum += lds_cnt[6 * w + f];
+            for (int w = 0; w < waves; ++w) sum += lds_cnt[kFates * w + f];
             if (sum) atomicAdd(slot + f, sum);
         }
         __threadfence();
@@ -285,7 +291,7 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
         unsigned long long done = atomicAdd(fin, 1ull);
         if (done == (unsigned long long)gridDim.x - 1ull) {
             __threadfence();
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < kFates; ++f) {
                 unsigned long long tot = 0;
                 for (int k = 0; k < kTallySlots; ++k) tot += atomicExch(S.tally + (size_t)k * kTallyStride + f, 0ull);
                 if (tot) atomicAdd(out.fate_counts + f, tot);
@@ -303,7 +309,7 @@ constexpr int kForwardBlocksPerCu = 8;
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                                 uint64_t first, uint64_t seed) {
     extern __shared__ uint32_t lds_stack[];
-    uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         uint64_t i = base + threadIdx.x;
@@ -319,7 +325,7 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
     uint64_t blocks = (n + kForwardBlock - 1) / kForwardBlock;
     uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
     if (blocks > cap) blocks = cap;
-    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + 6 * (kForwardBlock / 64) * sizeof(uint32_t);
+    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + kFates * (kForwardBlock / 64) * sizeof(uint32_t);
     hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
                        seed);
     return hipGetLastError();
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, D
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
-    uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     while (true) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(counter, (unsigned long long)chunk);
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, D
 
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, hipStream_t st) {
-    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t) + 6 * (block / 64) * sizeof(uint32_t);
+    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t) + kFates * (block / 64) * sizeof(uint32_t);
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk);
     return hipGetLastError();
 }

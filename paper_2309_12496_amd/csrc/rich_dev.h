@@ -17,6 +17,7 @@ namespace rich {
 constexpr uint32_t kStreamTag = 0x52494348u;   // fourth Philox counter word ("RICH")
 constexpr int kStackDepth = 32;                // per-lane traversal stack entries (LDS)
 constexpr int kMaxTable = 32;
+constexpr int kFates = 7;                      // photon fates, RICH_N_FATES
 constexpr int kTallySlots = 16;                // fate-count slots, one 128-byte line each
 constexpr int kTallyStride = 16;               // 64-bit words per slot
 constexpr int kTallyWords = kTallySlots * kTallyStride + kTallyStride;  // slots + finisher counter line
@@ -172,7 +173,13 @@ struct DevSource {
     double n_radiator;
     // explicit
     const float *ex_o, *ex_d, *ex_l;
+    // pre-propagation efficiency filter (0 materials and prefilter = 0: off)
+    int32_t prefilter;
+    int32_t pf_n;
+    int32_t pf_mats[4];
 };
+
+constexpr uint32_t kPrefilterBlock = 0x7FFFFFFFu;   // Philox block of the pre-filter draw
 
 struct DevOutputs {
     uint8_t *fate;

@@ -409,6 +409,7 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
         S.box_hi[a] = (float)d->box_hi[a];
     }
     S.n_seg = d->n_segments;
+    for (int i = 0; i < d->n_materials; ++i) s->mat_kind.push_back(d->materials[i].kind);
     s->n_segments = d->n_segments;
     s->nx = t.nx;
     s->ny = t.ny;

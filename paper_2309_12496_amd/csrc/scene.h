@@ -32,6 +32,7 @@ struct rich_scene {
     size_t partials_floats = 0;
 
     rich::DevScene dev{};
+    std::vector<int32_t> mat_kind;             // host copy of the material kinds
     int32_t n_segments = 0;
     int32_t n_top = 0;
     int32_t nx = 0, ny = 0;

@@ -510,9 +510,23 @@ __device__ __forceinline__ V3 surface_normal(const DevScene &S, const Hit &h, V3
     return n;
 }
 
+constexpr int kPrefiltered = 6;
+
+// Pre-propagation efficiency filter: keep the photon with probability
+// QE(lambda) * prod_k refl_k(lambda), as one accept-reject per photon.
+__device__ __forceinline__ bool prefilter_keep(const DevScene &S, const DetDev &det, const DevSource &src,
+                                               const Photon &ph, uint64_t seed, uint64_t g) {
+    float p = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
+    for (int k = 0; k < src.pf_n; ++k) p *= reflectivity(S, src.pf_mats[k], ph.lambda);
+    return u24(photon_block(seed, g, kPrefilterBlock).x) < p;
+}
+
+// Trace one photon.  With `efficiencies` false (photons kept by the
+// pre-filter) mirrors always reflect and the detector always detects.
 template <class Rec>
 __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, const Photon &ph, uint64_t seed,
-                                          uint64_t g, uint32_t *stk, int stride, PathEnd &end, Rec &rec) {
+                                          uint64_t g, uint32_t *stk, int stride, PathEnd &end, Rec &rec,
+                                          bool efficiencies = true) {
     V3 o = ph.o, d = ph.d;
     end.fate = kMaxBounces;
     end.pixel = -1;
@@ -542,8 +556,12 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             end.u = u;
             end.v = v;
             rec.detect(b, o, d, h.t);
-            float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
-            end.fate = ph.u_qe < qe ? kDetected : kQeRejected;
+            if (efficiencies) {
+                float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
+                end.fate = ph.u_qe < qe ? kDetected : kQeRejected;
+            } else {
+                end.fate = kDetected;
+            }
             break;
         }
         if (h.prim == S.prim_box) {
@@ -557,17 +575,19 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             end.fate = kAbsorbed;
             break;
         }
-        int bid = 1 + (b >> 2);
-        if (have != bid) {
-            blk = photon_block(seed, g, (uint32_t)bid);
-            have = bid;
-        }
-        int w = b & 3;
-        uint32_t word = w == 0 ? blk.x : (w == 1 ? blk.y : (w == 2 ? blk.z : blk.w));
-        float refl = reflectivity(S, mat, ph.lambda);
-        if (u24(word) >= refl) {
-            end.fate = kAbsorbedMirror;
-            break;
+        if (efficiencies) {
+            int bid = 1 + (b >> 2);
+            if (have != bid) {
+                blk = photon_block(seed, g, (uint32_t)bid);
+                have = bid;
+            }
+            int w = b & 3;
+            uint32_t word = w == 0 ? blk.x : (w == 1 ? blk.y : (w == 2 ? blk.z : blk.w));
+            float refl = reflectivity(S, mat, ph.lambda);
+            if (u24(word) >= refl) {
+                end.fate = kAbsorbedMirror;
+                break;
+            }
         }
         rec.reflect(b, h, o, d, P, n);
         V3 dr = fma3(-2.0f * dot(d, n), n, d);

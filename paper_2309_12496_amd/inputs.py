@@ -410,6 +410,14 @@ def point_source(origin=(0.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), beta=1.0,
             "lambda_min": float(lambda_min), "lambda_max": float(lambda_max)}
 
 
+def with_prefilter(src, mirror_materials=(MIRROR, MIRROR)):
+    """The same source with the paper's pre-propagation efficiency filter (Section 4.3):
+    keep each photon with probability QE * reflectivity of each listed mirror."""
+    out = dict(src)
+    out["prefilter"] = list(mirror_materials)
+    return out
+
+
 def explicit_source(o, d, lam):
     """Photons given one by one as origin, unit direction and wavelength (Section 4.2)."""
     return {"kind": "explicit", "o": f32(o).reshape(-1, 3), "d": f32(d).reshape(-1, 3),

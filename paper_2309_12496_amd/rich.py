@@ -25,7 +25,8 @@ if not os.path.exists(LIB_PATH):
 _L = C.CDLL(LIB_PATH)
 
 RICH_OK, RICH_EINVAL, RICH_ENOMEM, RICH_EDEVICE, RICH_ERANGE, RICH_EOVERFLOW, RICH_ESTATE = 0, -1, -2, -3, -4, -5, -6
-DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES = range(6)
+DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES, PREFILTERED = range(7)
+N_FATES = 7
 FLAG_HITLIST_OVERFLOW, FLAG_STACK_OVERFLOW, FLAG_PATH_OVERFLOW = 1, 2, 4
 SRC_TRACK, SRC_EXPLICIT = 0, 2
 MAX_TABLE = 32
@@ -84,17 +85,22 @@ class rich_scene_stats(C.Structure):
                 ("max_depth", C.c_int32), ("device_bytes", C.c_int64), ("build_seconds", C.c_double)]
 
 
+class rich_prefilter(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("n_materials", C.c_int32), ("materials", C.c_int32 * 4)]
+
+
 class rich_source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("origin", _d3), ("direction", _d3),
                 ("length", C.c_double), ("beta", C.c_double),
                 ("dev_o", C.c_void_p), ("dev_d", C.c_void_p), ("dev_lambda", C.c_void_p),
-                ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double)]
+                ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+                ("prefilter", rich_prefilter)]
 
 
 class rich_batch(C.Structure):
     _fields_ = [("dev_tracks", C.c_void_p), ("dev_offsets", C.c_void_p), ("n_tracks", C.c_int32),
                 ("reserved", C.c_int32), ("n_radiator", C.c_double), ("lambda_min", C.c_double),
-                ("lambda_max", C.c_double)]
+                ("lambda_max", C.c_double), ("prefilter", rich_prefilter)]
 
 
 class rich_outputs(C.Structure):
@@ -339,10 +345,20 @@ class Scene:
 
 # ------------------------------------------------------------------ sources and outputs
 
+def _set_prefilter(pf_struct, mats):
+    if mats is None:
+        return
+    pf_struct.enabled = 1
+    pf_struct.n_materials = len(mats)
+    for k, m in enumerate(mats):
+        pf_struct.materials[k] = int(m)
+
+
 def make_source(src, device="cuda"):
     """rich_source for a 'track' or 'explicit' source dict; returns (source, keepalive)."""
     s = rich_source()
     keep = []
+    _set_prefilter(s.prefilter, src.get("prefilter"))
     s.n_radiator = float(src.get("n_radiator", 1.0))
     s.lambda_min = float(src.get("lambda_min", 200.0))
     s.lambda_max = float(src.get("lambda_max", 600.0))
@@ -375,6 +391,7 @@ def make_batch(src, device="cuda"):
     b.n_radiator = float(src["n_radiator"])
     b.lambda_min = float(src["lambda_min"])
     b.lambda_max = float(src["lambda_max"])
+    _set_prefilter(b.prefilter, src.get("prefilter"))
     return b, [tracks, offsets], int(np.asarray(src["offsets"])[-1])
 
 
@@ -387,7 +404,7 @@ def alloc_outputs(scene, n, device="cuda", per_photon=True, hit_list_capacity=0)
         t["hit_xyz"] = torch.empty((n, 3), dtype=torch.float32, device=device)
         t["hit_uv"] = torch.empty((n, 2), dtype=torch.float32, device=device)
     t["histogram"] = torch.zeros(scene.nx * scene.ny, dtype=torch.int32, device=device)
-    t["fate_counts"] = torch.zeros(6, dtype=torch.int64, device=device)
+    t["fate_counts"] = torch.zeros(N_FATES, dtype=torch.int64, device=device)
     if hit_list_capacity:
         t["hit_list"] = torch.zeros((hit_list_capacity, 24), dtype=torch.uint8, device=device)
         t["hit_count"] = torch.zeros(1, dtype=torch.int64, device=device)

@@ -42,7 +42,7 @@ def _hist_counts_consistent(out, nx, ny):
     hist = to_np(out["histogram"]).astype(np.int64)
     counts = to_np(out["fate_counts"])
     assert counts.sum() == len(fate)
-    assert np.array_equal(counts, np.bincount(fate, minlength=6))
+    assert np.array_equal(counts, np.bincount(fate, minlength=7))
     assert np.array_equal(hist, np.bincount(pix[fate == 0], minlength=nx * ny))
 
 
@@ -176,7 +176,7 @@ def test_null_outputs_are_skipped(R, c1):
     import torch
     cfg, gs, _ = c1
     s, keep = R.make_source(cfg["source"])
-    t = {"fate_counts": torch.zeros(6, dtype=torch.int64, device="cuda")}
+    t = {"fate_counts": torch.zeros(7, dtype=torch.int64, device="cuda")}
     o = R.outputs_struct(t)
     R.rich_propagate(gs.handle, s, 10000, cfg["seed"], 0, o)
     torch.cuda.synchronize()
@@ -243,3 +243,33 @@ def test_batch_graph_replay_matches_eager_single_source(R):
         sl = slice(int(offs[k]), int(offs[k + 1]))
         agree = (to_np(one["fate"]) == first["fate"][sl]) & (to_np(one["pixel"]) == first["pixel"][sl])
         assert agree.mean() >= 0.999
+
+
+def test_prefilter_mode_parity(R, orc, c2):
+    """The paper's accept-reject before propagation (Section 4.3), photon by photon against the oracle."""
+    cfg, gs, os_ = c2
+    src = I.with_prefilter(cfg["source"])
+    n = 200_000
+    out = R.propagate(gs, src, n, cfg["seed"])
+    ref = orc.propagate(os_, src, n, cfg["seed"])
+    compare(out, ref, label="prefilter")
+    fate = to_np(out["fate"])
+    assert set(np.unique(fate)) <= {R.DETECTED, R.PREFILTERED, R.ABSORBED}
+    _hist_counts_consistent(out, gs.nx, gs.ny)
+
+
+def test_prefilter_batch_and_validation(R, orc):
+    cfg = I.config(3)
+    gs = R.Scene(cfg["scene"])
+    src = I.with_prefilter(cfg["source"])
+    out = R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(128, 128, 4))
+    ids = np.arange(0, cfg["n_photons"], 97, dtype=np.uint64)
+    ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv")}
+    compare(sub, ref, label="prefilter batch")
+    bad = I.with_prefilter(I.point_source(), mirror_materials=(I.ABSORBER,))
+    s, keep = R.make_source(bad)
+    t, o = R.alloc_outputs(gs, 10)
+    with pytest.raises(R.RichError) as e:
+        R.rich_propagate(gs.handle, s, 10, 1, 0, o)
+    assert e.value.code == R.RICH_EINVAL

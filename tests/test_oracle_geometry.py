@@ -309,3 +309,36 @@ def test_rejects_non_finite_vertex(orc):
     s["meshes"][0]["vertices"][0, 0, 0] = np.nan
     with pytest.raises(ValueError):
         orc.Scene(s)
+
+
+# ---------------------------------------------------------------- pre-propagation filter (Section 4.3)
+
+def test_prefilter_matches_roulette_in_law(orc):
+    """Accept-reject of QE x R x R before propagation and roulette at the surfaces give the same
+    detected-photon law when every photon meets two mirrors (C1): same detected fraction
+    E[R^2 QE], same wavelength distribution of detected photons."""
+    from scipy import stats
+    cfg = I.config(1)
+    n = 200_000
+    S = orc.Scene(cfg["scene"])
+    rou = orc.propagate(S, cfg["source"], n, cfg["seed"])
+    pre = orc.propagate(S, I.with_prefilter(cfg["source"]), n, cfg["seed"])
+    p = _expect(lambda R, Q: R * R * Q)
+    sigma = math.sqrt(n * p * (1 - p))
+    for res in (rou, pre):
+        assert abs(int((res["fate"] == orc.DETECTED).sum()) - n * p) < 5 * sigma
+    # pre-filter mode: photons are either rejected up front or detected (no roulette afterwards)
+    assert set(np.unique(pre["fate"])) <= {orc.DETECTED, orc.PREFILTERED}
+    _, _, lam = orc.generate(cfg["source"], n, cfg["seed"])
+    ks = stats.ks_2samp(lam[rou["fate"] == orc.DETECTED], lam[pre["fate"] == orc.DETECTED])
+    assert ks.pvalue > 1e-3
+    # kept photons land where roulette-mode photons that reach the detector land
+    on_r = np.isin(rou["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    kept = pre["fate"] == orc.DETECTED
+    assert np.allclose(pre["hit_xyz"][kept & on_r], rou["hit_xyz"][kept & on_r])
+
+
+def test_prefilter_rejects_non_mirror_material(orc):
+    src = I.with_prefilter(I.point_source(), mirror_materials=(I.ABSORBER,))
+    with pytest.raises(ValueError):
+        orc.propagate(I.scene_g1(), src, 10, seed=1)
