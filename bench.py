@@ -134,7 +134,7 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     s_ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 1, stream)
     a_ms = time_steps(lambda: R.rich_propagate_adjoint(sc.handle, None, b, n, cfg["seed"], 0, None, targets, mask,
-                                                       grad, loss, stream), steps, 1, stream)
+                                                       None, grad, loss, stream), steps, 1, stream)
     assert sc.status() == 0
     return {"workload": cfg["name"], "photons_per_step": n, "parameters": 6 * sc.n_segments,
             "forward_ms": s_ms, "adjoint_ms": a_ms, "ms_per_step": s_ms + a_ms,

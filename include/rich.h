@@ -288,12 +288,18 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
  *   dev_grad_uv != NULL: dev_grad_params = sum_i J_i^T dev_grad_uv[i];
  *   dev_targets != NULL (fused loss): L = (1/N) sum_i |uv_i - target_i|^2 over
  *     the N counted photons, dev_grad_params = dL/dp, *dev_loss = L.
+ *     dev_residual_cut (fused mode only, NULL = no cut) points to one float
+ *     on the device, read when the kernel runs: photons whose residual
+ *     |uv_i - target_i| exceeds it are not counted (outlier rejection for
+ *     fits; a negative or NaN cut leaves every photon out).  Giving it in dev_grad_uv
+ *     mode is RICH_EINVAL.
  * dev_grad_params [n_segments][6] is overwritten.  The sums are deterministic
  * (fixed reduction order). */
 rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
                                    uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
-                                   float *dev_grad_params, float *dev_loss, hipStream_t stream);
+                                   const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
+                                   hipStream_t stream);
 
 /* Synchronise the stream, return the device flags raised since the last call
  * (RICH_FLAG_*) and clear them.  Returns RICH_EOVERFLOW when any is set. */

@@ -341,14 +341,18 @@ def fate_counts(res):
     return np.bincount(res["fate"], minlength=N_FATES).astype(np.uint64)
 
 
-def mse_loss_and_grad(res, targets, mask, n_seg):
+def mse_loss_and_grad(res, targets, mask, n_seg, residual_cut=None):
     """Masked mean squared hit residual and its gradient through the oracle Jacobians.
 
     L = (1/N) sum_i |uv_i - target_i|^2 over photons in ``mask`` that reach the
-    detector; dL/dp = (2/N) sum_i J_i^T (uv_i - target_i) scattered to each
+    detector (and, given ``residual_cut``, whose |uv_i - target_i| does not
+    exceed it); dL/dp = (2/N) sum_i J_i^T (uv_i - target_i) scattered to each
     photon's segment.
     """
     use = mask.astype(bool) & np.isin(res["fate"], [DETECTED, QE_REJECTED])
+    if residual_cut is not None:
+        with np.errstate(invalid="ignore"):
+            use &= np.linalg.norm(res["hit_uv"] - targets, axis=1) <= residual_cut
     if np.any(res["segment"][use] == -2):
         raise ValueError("a masked photon hits two parametrised segments; its Jacobian is not tracked")
     nuse = int(use.sum())

@@ -45,3 +45,97 @@ def alignment_loss(scene, src, seed, targets, mask, n=None, params=None):
         scene.set_params(params)
     grad, loss = R.adjoint(scene, src, seed, n=n, targets=targets, mask=mask)
     return loss, grad
+
+
+# ------------------------------------------------------------------ alignment fit
+
+# Normalising scale of each parameter column (tx, ty [rad], R, dx, dy, dz [mm]):
+# Adam steps are taken in z = (p - p0) / scale.
+PARAM_SCALE = (1e-3, 1e-3, 10.0, 1.0, 1.0, 1.0)
+# Columns fitted by default.  The pivot shifts are left out: with tilts and
+# radius free, a shift of an analytic segment's pivot is degenerate with them
+# (only the centre of curvature and the radius are seen by the photons).
+FIT_TILTS_RADII = (True, True, True, False, False, False)
+
+
+def adam_fit(loss_and_grad, p0, steps=300, lr=0.1, lr_final=1e-4, scale=PARAM_SCALE, free=FIT_TILTS_RADII,
+             betas=(0.9, 0.999), eps=1e-12):
+    """Adam over the free columns of `p0` ([n_segments, 6]) with a cosine-decayed step size.
+
+    `loss_and_grad(p)` returns (loss, dL/dp) as tensors on p0's device; the
+    loop keeps everything there (no host synchronisation per step).  Returns
+    the final parameters and the loss of every step (at the parameters before
+    that step's update).
+    """
+    import math
+    p0 = torch.as_tensor(p0)
+    sc = torch.as_tensor(scale, dtype=p0.dtype, device=p0.device)[None, :]
+    fm = torch.as_tensor(free, dtype=p0.dtype, device=p0.device)[None, :]
+    z = torch.zeros_like(p0)
+    m = torch.zeros_like(p0)
+    v = torch.zeros_like(p0)
+    losses = []
+    b1, b2 = betas
+    for t in range(1, steps + 1):
+        p = p0 + z * sc
+        loss, grad = loss_and_grad(p)
+        losses.append(torch.as_tensor(loss, device=p0.device).reshape(()))
+        g = torch.as_tensor(grad, dtype=p0.dtype, device=p0.device).reshape(p0.shape) * sc * fm
+        m.mul_(b1).add_(g, alpha=1 - b1)
+        v.mul_(b2).addcmul_(g, g, value=1 - b2)
+        step = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * (t - 1) / steps))
+        mh = m / (1 - b1 ** t)
+        vh = v / (1 - b2 ** t)
+        z.sub_(step * mh / (vh.sqrt() + eps))
+    return p0 + z * sc, torch.stack(losses)
+
+
+def fit_alignment(scene, src, seed, targets, target_mask, params0=None, n=None, steps=600, lr=0.3, lr_final=1e-4,
+                  free=FIT_TILTS_RADII, outlier_cut=5.0, cut_floor=1e-3):
+    """Fit the segment parameters so that the photons' detector hits match `targets`.
+
+    Every step moves the mirrors on the device (rich_set_mirror_params: cap
+    centres, instance transforms and the top-level boxes are recomputed
+    there, nothing is rebuilt on the host) and runs one fused adjoint launch
+    that retraces the photons, forms the mean squared hit residual over the
+    photons in `target_mask` that still reach the pixel grid, and returns its
+    gradient.  Photon ids key the random numbers, so the same photons are
+    compared at every step.
+
+    Photons that cross onto another facet or segment than in the target run
+    carry residual jumps that the interior derivative cannot remove; they
+    would bias the fit.  With `outlier_cut` set, a step leaves out photons
+    whose residual exceeds outlier_cut x the previous step's RMS residual
+    + cut_floor (mm); the cut lives on the device, so the loop never waits
+    for the host.  Returns (params, losses); the scene is left at the fitted
+    parameters.
+    """
+    device = f"cuda:{scene.device}"
+    if params0 is None:
+        params0 = scene.params0
+    p0 = torch.as_tensor(params0, dtype=torch.float32, device=device).contiguous()
+    tgt = torch.as_tensor(targets, dtype=torch.float32, device=device).contiguous()
+    mask = torch.as_tensor(target_mask, device=device).to(torch.uint8).contiguous()
+    if src["kind"] == "batch":
+        b, keep, nb = R.make_batch(src, device)
+        s, n = None, nb if n is None else n
+    else:
+        s, keep = R.make_source(src, device)
+        b = None
+    if n is None:
+        raise ValueError("n is required for single sources")
+    cut = torch.full((1,), float("inf"), dtype=torch.float32, device=device) if outlier_cut else None
+
+    def loss_and_grad(p):
+        scene.set_params(p)
+        grad = torch.empty((scene.n_segments, 6), dtype=torch.float32, device=device)
+        loss = torch.empty(1, dtype=torch.float32, device=device)
+        R.rich_propagate_adjoint(scene.handle, s, b, n, seed, 0, None, tgt, mask, cut, grad, loss)
+        if cut is not None:
+            # no photon counted (loss exactly 0): open the cut again
+            cut.copy_(torch.where(loss > 0, loss.sqrt() * outlier_cut + cut_floor, torch.full_like(loss, float("inf"))))
+        return loss, grad
+
+    p, losses = adam_fit(loss_and_grad, p0, steps=steps, lr=lr, lr_final=lr_final, free=free)
+    scene.set_params(p)
+    return p, losses

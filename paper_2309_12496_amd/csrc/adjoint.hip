@@ -134,6 +134,12 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
     for (int j = lane; j < width; j += 64) acc[j] = 0.0f;
 
     const DetDev &det = *S.det;
+    // Squared residual cut; a negative or NaN cut admits no photon.
+    float cut2 = __builtin_inff();
+    if (a.residual_cut) {
+        float c = *a.residual_cut;
+        cut2 = c >= 0.0f ? c * c : -1.0f;
+    }
     const uint64_t nw = (uint64_t)gridDim.x * waves;
     const uint64_t gw = (uint64_t)blockIdx.x * waves + wave;
     for (uint64_t base = gw * 64; base < n; base += nw * 64) {
@@ -165,14 +171,16 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
         if (act) {
             if (a.targets) {
                 float du = end.u - a.targets[2 * i], dv = end.v - a.targets[2 * i + 1];
+                float r2 = du * du + dv * dv;
+                act = r2 <= cut2;
                 gu = 2.0f * du;
                 gv = 2.0f * dv;
-                loss = du * du + dv * dv;
+                loss = act ? r2 : 0.0f;
             } else {
                 gu = a.grad_uv[2 * i];
                 gv = a.grad_uv[2 * i + 1];
             }
-            cnt = 1.0f;
+            cnt = act ? 1.0f : 0.0f;
         }
         // detector plane
         V3 gP = v3(0.0f, 0.0f, 0.0f), gD = v3(0.0f, 0.0f, 0.0f);

@@ -452,11 +452,13 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
 rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
                                    uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
-                                   float *dev_grad_params, float *dev_loss, hipStream_t stream) {
+                                   const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
+                                   hipStream_t stream) {
     if (!s) return set_error(RICH_EINVAL, "scene is NULL");
     if ((src == nullptr) == (batch == nullptr)) return set_error(RICH_EINVAL, "give exactly one of src and batch");
     if ((dev_grad_uv == nullptr) == (dev_targets == nullptr))
         return set_error(RICH_EINVAL, "give exactly one of dev_grad_uv and dev_targets");
+    if (dev_residual_cut && !dev_targets) return set_error(RICH_EINVAL, "dev_residual_cut needs dev_targets");
     if (!dev_grad_params) return set_error(RICH_EINVAL, "dev_grad_params is NULL");
     if (s->n_segments == 0) return set_error(RICH_ESTATE, "scene has no parametrised segments");
     if (first_photon_id + n_photons < first_photon_id) return set_error(RICH_ERANGE, "photon id range wraps 2^64");
@@ -481,7 +483,8 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
             return set_error(RICH_ENOMEM, "adjoint partials allocation failed");
         s->partials_floats = need;
     }
-    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, s->d_partials, dev_grad_params, dev_loss, n_par};
+    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, s->d_partials, dev_grad_params, dev_loss,
+                  n_par};
     RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, n_blocks, stream));
     return RICH_OK;
 }

@@ -30,6 +30,7 @@ struct AdjointArgs {
     const float *grad_uv;       // [N][2] or null
     const float *targets;       // [N][2] or null
     const uint8_t *mask;        // [N] or null (all)
+    const float *residual_cut;  // [1] or null (fused-loss mode only)
     float *partials;            // [n_blocks][n_par + 2]
     float *grad;                // [n_seg][6]
     float *loss;                // [1] or null

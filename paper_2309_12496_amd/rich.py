@@ -124,7 +124,7 @@ _L.rich_propagate_batch.argtypes = [C.c_void_p, C.POINTER(rich_batch), C.c_uint6
 _L.rich_autotune.argtypes = [C.c_void_p, C.POINTER(rich_batch), C.c_uint64, C.c_uint64, C.POINTER(rich_tuning)]
 _L.rich_propagate_adjoint.argtypes = [C.c_void_p, C.POINTER(rich_source), C.POINTER(rich_batch), C.c_uint64,
                                       C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                      C.c_void_p, C.c_void_p]
+                                      C.c_void_p, C.c_void_p, C.c_void_p]
 _L.rich_get_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
 _L.rich_last_error.restype = C.c_char_p
 _L.rich_version.restype = C.c_char_p
@@ -199,11 +199,12 @@ def rich_autotune(handle, batch, n_photons, seed):
 
 
 def rich_propagate_adjoint(handle, source, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets,
-                           dev_mask, dev_grad_params, dev_loss, stream=None):
+                           dev_mask, dev_residual_cut, dev_grad_params, dev_loss, stream=None):
     _check(_L.rich_propagate_adjoint(handle, None if source is None else C.byref(source),
                                      None if batch is None else C.byref(batch), int(n_photons), int(seed),
                                      int(first_photon_id), _ptr(dev_grad_uv), _ptr(dev_targets), _ptr(dev_mask),
-                                     _ptr(dev_grad_params), _ptr(dev_loss), _stream(stream)))
+                                     _ptr(dev_residual_cut), _ptr(dev_grad_params), _ptr(dev_loss),
+                                     _stream(stream)))
 
 
 def rich_get_status(handle, stream=None):
@@ -318,6 +319,7 @@ class Scene:
         det = scene["detector"]
         self.nx, self.ny = int(det["nx"]), int(det["ny"])
         self.n_segments = len(scene["segments"]["radius0"])
+        self.params0 = np.array(scene["params"] if params is None else params, np.float32)
 
     def info(self):
         return rich_scene_info(self.handle)
@@ -454,11 +456,13 @@ def tuning(block, chunk, blocks_per_cu):
     return rich_tuning(int(block), int(chunk), int(blocks_per_cu), 0)
 
 
-def adjoint(scene, src, seed, n=None, first_id=0, grad_uv=None, targets=None, mask=None, stream=None):
+def adjoint(scene, src, seed, n=None, first_id=0, grad_uv=None, targets=None, mask=None, residual_cut=None,
+            stream=None):
     """Reverse-mode gradient of the hits w.r.t. the segment parameters at the scene's current parameters.
 
     Exactly one of grad_uv ([N,2] upstream dL/d(u,v)) and targets ([N,2], fused mean-squared loss) is
-    given.  Returns (grad [n_segments, 6] float32 tensor, loss [1] tensor).
+    given; residual_cut (fused mode, mm) leaves out photons whose |uv - target| exceeds it.
+    Returns (grad [n_segments, 6] float32 tensor, loss [1] tensor).
     """
     device = f"cuda:{scene.device}"
     keep = []
@@ -481,9 +485,10 @@ def adjoint(scene, src, seed, n=None, first_id=0, grad_uv=None, targets=None, ma
     gu = dev(grad_uv, torch.float32)
     tg = dev(targets, torch.float32)
     mk = dev(mask, torch.uint8)
+    rc = None if residual_cut is None else dev(torch.as_tensor([float(residual_cut)]), torch.float32)
     grad = torch.zeros((scene.n_segments, 6), dtype=torch.float32, device=device)
     loss = torch.zeros(1, dtype=torch.float32, device=device)
-    rich_propagate_adjoint(scene.handle, s, b, n, seed, first_id, gu, tg, mk, grad, loss, stream)
-    keep += [gu, tg, mk]
+    rich_propagate_adjoint(scene.handle, s, b, n, seed, first_id, gu, tg, mk, rc, grad, loss, stream)
+    keep += [gu, tg, mk, rc]
     grad._keep = keep
     return grad, loss

@@ -184,3 +184,85 @@ def test_meshed_segments_forward_and_gradient(R, orc):
     assert gs.status() == 0
     assert abs(float(loss) / p["loss"] - 1) < 1e-4
     grad_close(to_np(grad), p["grad"], label="meshed")
+
+
+def _cut_in_gap(r, lo_q=0.3, hi_q=0.7, clearance=5e-3):
+    """A residual cut between two FP64 residuals far enough apart that FP32 cannot flip a photon."""
+    s = np.sort(r[np.isfinite(r)])
+    lo, hi = int(lo_q * len(s)), int(hi_q * len(s))
+    gaps = s[lo + 1:hi + 1] - s[lo:hi]
+    j = lo + int(np.argmax(gaps))
+    assert s[j + 1] - s[j] > 2 * clearance
+    return 0.5 * (s[j] + s[j + 1])
+
+
+def test_residual_cut_matches_oracle(R, orc, c4small):
+    """Fused loss with dev_residual_cut: photons beyond the cut are left out of loss, count and gradient."""
+    import torch
+    p = c4small
+    r = np.linalg.norm(p["cur"]["hit_uv"] - p["target"]["hit_uv"], axis=1)
+    cut = _cut_in_gap(np.where(p["mask"], r, np.nan))
+    loss_ref, grad_ref, nuse = orc.mse_loss_and_grad(p["cur"], p["target"]["hit_uv"], p["mask"],
+                                                     p["scene"]["params"].shape[0], residual_cut=cut)
+    assert 0.2 * p["nuse"] < nuse < 0.8 * p["nuse"]
+    gs = R.Scene(p["scene"])
+    grad, loss = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"], residual_cut=cut)
+    assert abs(float(loss) / loss_ref - 1) < 1e-4
+    grad_close(to_np(grad), grad_ref, label="residual cut")
+    # a NaN cut admits no photon; the cut is refused in upstream-gradient mode
+    grad, loss = R.adjoint(gs, p["src"], p["seed"], targets=p["target"]["hit_uv"], mask=p["mask"],
+                           residual_cut=float("nan"))
+    assert float(loss) == 0.0 and not to_np(grad).any()
+    b, keep, n = R.make_batch(p["src"])
+    g = torch.zeros((gs.n_segments, 6), device="cuda")
+    one = torch.ones(1, device="cuda")
+    gin = torch.zeros((n, 2), device="cuda")
+    with pytest.raises(R.RichError) as e:
+        R.rich_propagate_adjoint(gs.handle, None, b, n, p["seed"], 0, gin, None, None, one, g, None)
+    assert e.value.code == R.RICH_EINVAL
+
+
+def _fit_problem(orc, k, scene, n_tracks, per_track, min_photons):
+    rng = np.random.default_rng(1000 + k)
+    src = I.batch_source(I.sample_tracks(rng, n_tracks), np.full(n_tracks, per_track))
+    n, seed = n_tracks * per_track, I.SEED_BASE + k
+    tp = I.perturbed_params(k, scene)
+    tgt = orc.propagate(orc.Scene(scene, params=tp), src, n, seed, jacobian=True)
+    on = np.isin(tgt["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    seg = tgt["segment"][on & (tgt["segment"] >= 0)]
+    lit = np.bincount(seg, minlength=tp.shape[0]) >= min_photons
+    return src, seed, tp.astype(np.float64), tgt, on, lit
+
+
+def test_alignment_fit_recovers_analytic_misalignment(R, orc):
+    """Adam through the fused device adjoint recovers the seeded tilts and radii of the imaged G4 segments.
+
+    Targets are the oracle's FP64 hits at the misalignment; every step moves the
+    caps on the device and retraces the same 1e5 photons.
+    """
+    from paper_2309_12496_amd.align import fit_alignment
+    scene = I.scene_g4()
+    src, seed, tp, tgt, on, lit = _fit_problem(orc, 4, scene, 1000, 100, 100)
+    assert lit.sum() >= 4
+    gs = R.Scene(scene)
+    p, losses = fit_alignment(gs, src, seed, tgt["hit_uv"], on, steps=600, lr=0.3)
+    p, losses = to_np(p).astype(np.float64), to_np(losses)
+    assert gs.status() == 0
+    assert losses[-1] < 1e-6 * losses[0], (losses[0], losses[-1])
+    assert np.abs(p[lit, :2] - tp[lit, :2]).max() < 0.5e-6        # rad; perturbation sigma 0.5e-3
+    assert np.abs(p[lit, 2] - tp[lit, 2]).max() < 0.1             # mm; perturbation sigma 5
+    assert np.array_equal(p[~lit], np.asarray(scene["params"], np.float32)[~lit].astype(np.float64))
+
+
+def test_alignment_fit_recovers_meshed_tilts(R, orc):
+    """Meshed segments through their instance transforms, outliers cut on the device: tilts recovered."""
+    from paper_2309_12496_amd.align import fit_alignment
+    scene = I.scene_g5(seg_quads=(30, 50), flat_tiles=4)
+    src, seed, tp, tgt, on, lit = _fit_problem(orc, 5, scene, 1000, 100, 100)
+    assert lit.sum() >= 4
+    gs = R.Scene(scene)
+    p, losses = fit_alignment(gs, src, seed, tgt["hit_uv"], on, steps=600, lr=0.3,
+                              free=(True, True, False, False, False, False))
+    p = to_np(p).astype(np.float64)
+    assert gs.status() == 0
+    assert np.abs(p[lit, :2] - tp[lit, :2]).max() < 0.5e-6
