@@ -12,8 +12,10 @@ flat mirror, 10k-triangle enclosure) with 1e7 photons from one point
 emitter, plain forward.  The other forms of the metric are reported under
 "forms": batched (4096 Poisson-sized tracks, one persistent launch replayed
 from a HIP graph), forward+adjoint (4x4 segmented mirror, 1e6 photons, 96
-parameters), the analytic scene (1e5 photons per call, and 1e8 in one call),
-and the large scene (1e8 photons, 2M triangles, 192 parameters).
+parameters), an Adam alignment fit on the same scene, the headline workload
+with the pre-propagation efficiency filter, the analytic scene (1e5 photons
+per call, and 1e8 in one call), and the large scene (1e8 photons, 2M
+triangles, 192 parameters).
 Prints one JSON line.
 """
 
@@ -51,7 +53,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-forms", action="store_true", help="only the headline workload")
-    p.add_argument("--forms", default="c1,batched,adjoint,large", help="comma list of extra forms")
+    p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large", help="comma list of extra forms")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
@@ -142,6 +144,60 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
             "loss_mm2": float(loss), "masked_photons": int(mask.sum())}
 
 
+def form_align_fit(R, I, stream, steps):
+    """Adam alignment fit of the segmented mirror: one set_params + one fused adjoint launch per step.
+
+    Targets are the device hits at the seeded misalignment; the fit starts from
+    the nominal geometry.  Reports the step rate and how far the fitted tilts
+    and radii are from the misalignment, over the segments the photons reach
+    (the only ones whose parameters move).
+    """
+    import numpy as np
+    import torch
+    from paper_2309_12496_amd.align import fit_alignment
+    cfg = I.config(4)
+    sc = R.Scene(cfg["scene"])
+    sc.set_params(cfg["target_params"])
+    tgt = R.propagate_batch(sc, cfg["source"], cfg["seed"], tune=R.tuning(256, 256, 4))
+    on = tgt["fate"] <= R.QE_REJECTED
+    uv = tgt["hit_uv"].nan_to_num(0.0)
+    del tgt
+    fit_alignment(sc, cfg["source"], cfg["seed"], uv, on, steps=3)          # warm-up
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    p, losses = fit_alignment(sc, cfg["source"], cfg["seed"], uv, on, steps=steps, lr=0.3)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    assert sc.status() == 0
+    p = p.cpu().numpy().astype(np.float64)
+    p0 = np.asarray(cfg["scene"]["params"], np.float32).astype(np.float64)
+    tp = np.asarray(cfg["target_params"], np.float64)
+    moved = np.any(p != p0, axis=1)
+    n = cfg["n_photons"]
+    return {"workload": cfg["name"] + ", Adam fit of tilts and radii from the nominal geometry",
+            "photons_per_step": n, "steps": steps, "ms_per_step": ms, "photons_per_s": n / (ms * 1e-3),
+            "loss_first_mm2": float(losses[0]), "loss_last_mm2": float(losses[-1]),
+            "segments_fitted": int(moved.sum()),
+            "max_tilt_error_rad": float(np.abs(p[moved, :2] - tp[moved, :2]).max()),
+            "max_radius_error_mm": float(np.abs(p[moved, 2] - tp[moved, 2]).max())}
+
+
+def form_prefilter(R, I, stream, steps):
+    """The headline workload with the accept-reject of QE x R x R before propagation."""
+    cfg = I.config(2)
+    sc = R.Scene(cfg["scene"])
+    s, keep = R.make_source(I.with_prefilter(cfg["source"]))
+    n = cfg["n_photons"]
+    t, o = R.alloc_outputs(sc, n)
+    ms = time_steps(lambda: R.rich_propagate(sc.handle, s, n, cfg["seed"], 0, o, stream), steps, 2, stream)
+    assert sc.status() == 0
+    kept = n - int(t["fate_counts"][R.PREFILTERED]) // (steps + 2)
+    return {"workload": cfg["name"] + ", pre-filtered", "photons_per_step": n, "ms_per_step": ms,
+            "emitted_photons_per_s": n / (ms * 1e-3), "kept_photons_per_step": kept,
+            "kept_photons_per_s": kept / (ms * 1e-3)}
+
+
 def form_c1(R, I, stream, steps):
     cfg = I.config(1)
     sc = R.Scene(cfg["scene"])
@@ -223,6 +279,10 @@ def main():
             forms["batched"] = form_batched(R, I, stream, half)
         if "adjoint" in want:
             forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half)
+        if "fit" in want:
+            forms["align_fit"] = form_align_fit(R, I, stream, 300)
+        if "prefilter" in want:
+            forms["prefilter"] = form_prefilter(R, I, stream, half)
         if "large" in want:
             forms["large_fwd_adjoint"] = _fwd_adjoint(R, I, I.config(5), stream, 3)
         line["forms"] = forms
