@@ -54,6 +54,7 @@ class Source(C.Structure):
         ("ex_o", _dp), ("ex_d", _dp), ("ex_lambda", _dp),
         ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
         ("prefilter", C.c_int32), ("pf_n", C.c_int32), ("pf_mats", C.c_int32 * 4),
+        ("n_disp", C.c_int32), ("disp_x", C.c_double * 32), ("disp_n", C.c_double * 32),
     ]
 
 
@@ -61,6 +62,7 @@ class Outputs(C.Structure):
     _fields_ = [
         ("fate", C.POINTER(C.c_uint8)), ("pixel", _ip), ("hit_xyz", _dp), ("hit_uv", _dp),
         ("edge_margin", _dp), ("pixel_margin", _dp), ("roulette_margin", _dp), ("n_bounce", _ip), ("segment", _ip), ("jac", _dp),
+        ("hit_time", _dp),
     ]
 
 
@@ -102,6 +104,7 @@ def lib():
         L.orc_prim_base_triangles.argtypes = [C.c_void_p]
         L.orc_philox4x32_r.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int,
                                        C.POINTER(C.c_uint32)]
+        L.orc_cherenkov_yield.argtypes = [C.POINTER(Source), C.c_double, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -240,6 +243,15 @@ def _source(src, keep):
         s.pf_n = len(pf)
         for k, m in enumerate(pf):
             s.pf_mats[k] = int(m)
+    disp = src.get("dispersion")
+    if disp is not None:
+        x = np.asarray(disp["lambda"], np.float64)
+        nn = np.asarray(disp["index"], np.float64)
+        if len(x) > 32 or len(x) != len(nn):
+            raise ValueError("dispersion: up to 32 (lambda, n) nodes")
+        s.n_disp = len(x)
+        s.disp_x[:len(x)] = list(x)
+        s.disp_n[:len(x)] = list(nn)
     if kind == "track":
         s.kind = SRC_TRACK
         s.origin[:] = list(src["origin"])
@@ -265,6 +277,16 @@ def _source(src, keep):
     return s
 
 
+def cherenkov_yield(src, beta):
+    """Cherenkov photons per mm of track at velocity beta (Frank-Tamm) for the source's radiator."""
+    keep = []
+    s = _source(dict(src, kind="explicit", o=np.zeros((0, 3)), d=np.zeros((0, 3)), **{"lambda": np.zeros(0)}), keep)
+    out = C.c_double()
+    if lib().orc_cherenkov_yield(C.byref(s), float(beta), C.byref(out)) != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out.value
+
+
 def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, threads=None, ids=None):
     """Trace photons first_id .. first_id+n-1 (or the photon ids in ``ids``); returns numpy arrays."""
     if not isinstance(scene, Scene):
@@ -279,7 +301,7 @@ def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, thr
         "fate": np.zeros(n, np.uint8), "pixel": np.zeros(n, np.int32),
         "hit_xyz": np.zeros((n, 3)), "hit_uv": np.zeros((n, 2)),
         "edge_margin": np.zeros(n), "pixel_margin": np.zeros(n), "roulette_margin": np.zeros(n),
-        "n_bounce": np.zeros(n, np.int32),
+        "n_bounce": np.zeros(n, np.int32), "hit_time": np.zeros(n),
     }
     o = Outputs()
     o.fate = _ptr(res["fate"], C.c_uint8)
@@ -290,6 +312,7 @@ def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, thr
     o.pixel_margin = _ptr(res["pixel_margin"], C.c_double)
     o.roulette_margin = _ptr(res["roulette_margin"], C.c_double)
     o.n_bounce = _ptr(res["n_bounce"], C.c_int32)
+    o.hit_time = _ptr(res["hit_time"], C.c_double)
     if jacobian:
         res["segment"] = np.zeros(n, np.int32)
         res["jac"] = np.zeros((n, 2, 6))

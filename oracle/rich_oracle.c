@@ -572,7 +572,52 @@ static void onb(v3 n, v3 *b1, v3 *b2)
     *b2 = V(b, sign + n.y * n.y * a, -n.y);
 }
 
-typedef struct { v3 o, d; double lambda; double u_qe; } photon;
+/* t0: emission time (ns after the track origin passes P0); ng: group index
+ * of the radiator at the photon's wavelength; margin: smallest |u - p| over
+ * the wavelength accept-reject decisions. */
+typedef struct { v3 o, d; double lambda; double u_qe; double t0, ng, margin; } photon;
+
+#define C_MM_PER_NS 299.792458            /* speed of light in vacuum */
+#define FINE_STRUCTURE (1.0 / 137.035999084)
+#define DISP_BLOCK 0x7FFFFFFEu            /* Philox blocks of the wavelength retries count down from here */
+#define DISP_MAX_TRIES 64
+
+/* Refractive index of the radiator at lambda (Section 3: the cone angle
+ * follows n); piecewise linear through the dispersion table, clamped. */
+static double index_at(const orc_source *src, double lambda)
+{
+    return src->n_disp > 0 ? table(src->n_disp, src->disp_x, src->disp_n, lambda) : src->n_radiator;
+}
+
+/* Group index n - lambda dn/dlambda: the speed c/n_g at which the photon's
+ * light travels.  dn/dlambda is the table segment's slope (0 outside). */
+static double group_index_at(const orc_source *src, double lambda)
+{
+    if (src->n_disp < 2) return index_at(src, lambda);
+    const double *x = src->disp_x, *y = src->disp_n;
+    int n = src->n_disp;
+    if (lambda < x[0] || lambda >= x[n - 1]) return index_at(src, lambda);
+    int i = 0;
+    while (i + 1 < n - 1 && lambda >= x[i + 1]) ++i;
+    double slope = (y[i + 1] - y[i]) / (x[i + 1] - x[i]);
+    return index_at(src, lambda) - lambda * slope;
+}
+
+/* Frank-Tamm spectral weight 1 - 1/(beta n)^2, zero below threshold. */
+static double ft_weight(double n, double beta)
+{
+    double w = 1.0 - 1.0 / (beta * beta * n * n);
+    return w > 0.0 ? w : 0.0;
+}
+
+/* Largest refractive index over [lambda_min, lambda_max] (at a table node or an end). */
+static double max_index(const orc_source *src)
+{
+    double m = fmax(index_at(src, src->lambda_min), index_at(src, src->lambda_max));
+    for (int k = 0; k < src->n_disp; ++k)
+        if (src->disp_x[k] > src->lambda_min && src->disp_x[k] < src->lambda_max) m = fmax(m, src->disp_n[k]);
+    return m;
+}
 
 #define PREFILTER_BLOCK 0x7FFFFFFFu
 
@@ -614,6 +659,9 @@ static void make_photon(const orc_source *src, uint64_t seed, uint64_t g, uint64
         ph->o = vload(src->ex_o + 3 * i);
         ph->d = vload(src->ex_d + 3 * i);
         ph->lambda = src->ex_lambda[i];
+        ph->t0 = 0.0;
+        ph->ng = group_index_at(src, ph->lambda);
+        ph->margin = INFINITY;
         return;
     }
     v3 P0, T;
@@ -634,14 +682,36 @@ static void make_photon(const orc_source *src, uint64_t seed, uint64_t g, uint64
     /* wavelength: inverse CDF of dN/dlambda ~ 1/lambda^2 on [lambda_min, lambda_max] */
     double a = 1.0 / src->lambda_min, b = 1.0 / src->lambda_max;
     ph->lambda = 1.0 / (a - u_lam * (a - b));
-    /* Cherenkov cone (Section 3) */
-    double ct = 1.0 / (src->n_radiator * beta);
+    ph->margin = INFINITY;
+    if (src->n_disp > 0) {
+        /* With dispersion the Frank-Tamm spectrum is (1 - 1/(beta n)^2)/lambda^2:
+         * accept the 1/lambda^2 draw with probability w(lambda)/w_max, else draw
+         * again.  Attempt 0 keeps the draw above (its acceptance uniform is word
+         * 0 of block DISP_BLOCK); attempt k >= 1 takes words 1 (wavelength) and
+         * 0 (acceptance) of block DISP_BLOCK - k.  After DISP_MAX_TRIES
+         * rejections the last draw stands. */
+        double wmax = ft_weight(max_index(src), beta);
+        for (int k = 0; k < DISP_MAX_TRIES; ++k) {
+            uint32_t wb[4];
+            photon_block(seed, g, DISP_BLOCK - (uint32_t)k, wb);
+            if (k > 0) ph->lambda = 1.0 / (a - u24(wb[1]) * (a - b));
+            double p = ft_weight(index_at(src, ph->lambda), beta) / wmax;
+            double u = u24(wb[0]);
+            ph->margin = fmin(ph->margin, fabs(u - p));
+            if (u < p) break;
+        }
+    }
+    /* Cherenkov cone (Section 3) at the photon's own refractive index */
+    double ct = 1.0 / (index_at(src, ph->lambda) * beta);
     double st = sqrt(1.0 - ct * ct);
     double phi = 2.0 * M_PI * u_phi;
     v3 e1, e2;
     onb(T, &e1, &e2);
     ph->d = vadd(vmul(T, ct), vmul(vadd(vmul(e1, cos(phi)), vmul(e2, sin(phi))), st));
     ph->o = vadd(P0, vmul(T, u_s * L));
+    /* the track moves at beta c from P0 */
+    ph->t0 = u_s * L / (beta * C_MM_PER_NS);
+    ph->ng = group_index_at(src, ph->lambda);
 }
 
 int orc_generate(const orc_scene *s, const orc_source *src, uint64_t n, uint64_t seed, uint64_t first_id,
@@ -833,8 +903,9 @@ static void trace_photon(const job *jb, uint64_t i)
     v3 o = ph.o, d = ph.d;
     int64_t nc = s->d.n_cap, nr = s->d.n_rect, det_id = nc + nr, box_id = nc + nr + 1, tb = nc + nr + 2;
     int fate = ORC_MAX_BOUNCES, pixel = -1, nb = 0;
-    double hxyz[3] = {NAN, NAN, NAN}, huv[2] = {NAN, NAN};
-    double emargin = INFINITY, rmargin = INFINITY, pmargin = INFINITY;
+    double hxyz[3] = {NAN, NAN, NAN}, huv[2] = {NAN, NAN}, htime = NAN;
+    double travelled = 0.0;         /* path length so far (mm) */
+    double emargin = INFINITY, rmargin = ph.margin, pmargin = INFINITY;
     pathrec path[64];
     int npath = 0;
     uint32_t blk[4];
@@ -847,7 +918,7 @@ static void trace_photon(const job *jb, uint64_t i)
             fate = ORC_PREFILTERED;
             nloop = 0;
         }
-        rmargin = m;
+        rmargin = fmin(m, ph.margin);
         eff = 0;
     }
 
@@ -858,6 +929,7 @@ static void trace_photon(const job *jb, uint64_t i)
         ++nb;
         if (npath < 64) { path[npath].prim = h.prim; path[npath].root = h.root; ++npath; }
         v3 P = vadd(o, vmul(d, h.t));
+        travelled += h.t;
         if (h.prim == det_id) {
             v3 n = vload(s->d.det_n), c = vload(s->d.det_c);
             if (vdot(d, n) >= 0) { fate = ORC_ABSORBED; break; }
@@ -870,6 +942,7 @@ static void trace_photon(const job *jb, uint64_t i)
             if (fi < 0 || fi >= s->d.det_nx || fj < 0 || fj >= s->d.det_ny) { fate = ORC_ABSORBED; break; }
             pixel = (int)fj * s->d.det_nx + (int)fi;
             hxyz[0] = P.x; hxyz[1] = P.y; hxyz[2] = P.z;
+            htime = ph.t0 + travelled * ph.ng / C_MM_PER_NS;
             huv[0] = u; huv[1] = v;
             if (eff) {
                 double qe = table(s->d.n_qe, s->d.qe_x, s->d.qe_y, ph.lambda);
@@ -930,6 +1003,7 @@ static void trace_photon(const job *jb, uint64_t i)
     if (out->pixel) out->pixel[i] = pixel;
     if (out->hit_xyz) for (int a = 0; a < 3; ++a) out->hit_xyz[3 * i + a] = hxyz[a];
     if (out->hit_uv) { out->hit_uv[2 * i] = huv[0]; out->hit_uv[2 * i + 1] = huv[1]; }
+    if (out->hit_time) out->hit_time[i] = htime;
     if (out->edge_margin) out->edge_margin[i] = emargin;
     if (out->roulette_margin) out->roulette_margin[i] = rmargin;
     if (out->pixel_margin) out->pixel_margin[i] = pmargin;
@@ -972,10 +1046,19 @@ static int propagate_any(const orc_scene *s, const orc_source *src, const uint64
             set_err("bad source spectrum");
             return -1;
         }
-        if (src->kind == ORC_SRC_TRACK && !(src->n_radiator * src->beta > 1.0)) { set_err("n beta <= 1"); return -1; }
+        if (src->n_disp < 0 || src->n_disp > ORC_MAX_TABLE) { set_err("dispersion: 0..32 nodes"); return -1; }
+        for (int k = 0; k < src->n_disp; ++k) {
+            if (!(src->disp_n[k] >= 1.0) || (k > 0 && !(src->disp_x[k] > src->disp_x[k - 1]))) {
+                set_err("dispersion: increasing wavelengths and indices >= 1");
+                return -1;
+            }
+        }
+        /* the largest index over the band must be above threshold for every track */
+        double nmax = src->n_disp > 0 ? max_index(src) : src->n_radiator;
+        if (src->kind == ORC_SRC_TRACK && !(nmax * src->beta > 1.0)) { set_err("n beta <= 1"); return -1; }
         if (src->kind == ORC_SRC_BATCH) {
             for (int64_t k = 0; k < src->n_tracks; ++k)
-                if (!(src->n_radiator * src->tracks[8 * k + 7] > 1.0)) { set_err("n beta <= 1"); return -1; }
+                if (!(nmax * src->tracks[8 * k + 7] > 1.0)) { set_err("n beta <= 1"); return -1; }
             uint64_t total = src->offsets[src->n_tracks];
             if (!ids && first_id + n > total) { set_err("photon id beyond the batch"); return -1; }
             if (ids)
@@ -1022,4 +1105,59 @@ int orc_propagate_ids(const orc_scene *s, const orc_source *src, const uint64_t 
                       int use_bvh, int with_jacobian, int n_threads, const orc_outputs *out)
 {
     return propagate_any(s, src, ids, n, seed, 0, use_bvh, with_jacobian, n_threads, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cherenkov yield (Frank-Tamm)                                              */
+/* ------------------------------------------------------------------------ */
+
+static double yield_integrand(const orc_source *src, double beta, double lambda_nm)
+{
+    return ft_weight(index_at(src, lambda_nm), beta) / (lambda_nm * lambda_nm);
+}
+
+int orc_cherenkov_yield(const orc_source *src, double beta, double *photons_per_mm)
+{
+    if (!src || !photons_per_mm) { set_err("null argument"); return -1; }
+    if (!(src->lambda_min > 0) || !(src->lambda_max > src->lambda_min) || !(beta > 0)) {
+        set_err("bad spectrum or beta");
+        return -1;
+    }
+    if (src->n_disp < 0 || src->n_disp > ORC_MAX_TABLE) { set_err("dispersion: 0..32 nodes"); return -1; }
+    /* breakpoints: the band ends and every table node inside the band; the
+     * threshold crossing inside a segment is handled by refining: composite
+     * Simpson with 20000 panels per piece of the piecewise-linear n */
+    double bp[ORC_MAX_TABLE + 2];
+    int nb = 0;
+    bp[nb++] = src->lambda_min;
+    for (int k = 0; k < src->n_disp; ++k)
+        if (src->disp_x[k] > src->lambda_min && src->disp_x[k] < src->lambda_max) bp[nb++] = src->disp_x[k];
+    bp[nb++] = src->lambda_max;
+    double integral = 0.0;   /* of w / lambda^2 over lambda in nm, units 1/nm */
+    const int panels = 20000;
+    for (int q = 0; q + 1 < nb; ++q) {
+        double lo = bp[q], hi = bp[q + 1];
+        /* threshold inside this piece: split there so Simpson sees no kink */
+        double cut[3] = {lo, hi, hi};
+        int nc = 2;
+        double wlo = 1.0 - 1.0 / (beta * beta * index_at(src, lo) * index_at(src, lo));
+        double whi = 1.0 - 1.0 / (beta * beta * index_at(src, hi) * index_at(src, hi));
+        if ((wlo > 0) != (whi > 0)) {
+            /* n is linear on the piece: solve n(lambda) = 1/beta */
+            double nl = index_at(src, lo), nh = index_at(src, hi);
+            double lam = lo + (1.0 / beta - nl) / (nh - nl) * (hi - lo);
+            cut[1] = lam;
+            cut[2] = hi;
+            nc = 3;
+        }
+        for (int c = 0; c + 1 < nc; ++c) {
+            double a = cut[c], b = cut[c + 1];
+            double h = (b - a) / panels, sum = yield_integrand(src, beta, a) + yield_integrand(src, beta, b);
+            for (int j = 1; j < panels; ++j) sum += (j % 2 ? 4.0 : 2.0) * yield_integrand(src, beta, a + j * h);
+            integral += sum * h / 3.0;
+        }
+    }
+    /* lambda in mm: integral of w / lambda_mm^2 d lambda_mm = 1e6 x the nm integral */
+    *photons_per_mm = 2.0 * M_PI * FINE_STRUCTURE * 1e6 * integral;
+    return 0;
 }

@@ -88,6 +88,10 @@ typedef struct {
     double n_radiator, lambda_min, lambda_max;
     /* pre-propagation filter (Section 4.3): keep with probability QE * prod refl(mats) */
     int32_t prefilter, pf_n, pf_mats[4];
+    /* dispersion of the radiator (0 nodes: n = n_radiator for every wavelength):
+     * n(lambda) piecewise linear through (disp_x, disp_n), clamped outside */
+    int32_t n_disp;
+    double disp_x[ORC_MAX_TABLE], disp_n[ORC_MAX_TABLE];
 } orc_source;
 
 typedef struct orc_scene orc_scene;
@@ -104,7 +108,13 @@ typedef struct {
     int32_t *n_bounce;         /* surfaces hit */
     int32_t *segment;          /* parametrised segment hit (-1 none, -2 more than one) */
     double *jac;               /* [n][2][6] d(u,v)/d(segment params), NaN when undefined */
+    double *hit_time;          /* [n] ns from the track origin to the detector hit, NaN unless DETECTED / QE_REJECTED */
 } orc_outputs;
+
+/* Cherenkov photons per mm of track (Frank-Tamm): 2 pi alpha times the
+ * integral over [lambda_min, lambda_max] of (1 - 1/(beta n(lambda))^2)^+ / lambda^2,
+ * lambda in mm; n from the source's dispersion table or n_radiator. */
+int orc_cherenkov_yield(const orc_source *src, double beta, double *photons_per_mm);
 
 /* Philox4x32-10: ctr[4], key[2] -> out[4]. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -398,9 +398,63 @@ def scene_t0(detector_half=600.0, n_pix=400, pitch=3.0):
     }
 
 
+def scene_t1(radius=2000.0, detector_z=100.0, n_pix=200, pitch=3.0):
+    """Isochronism test scene: a concave mirror of radius `radius` centred on the
+    origin (pivot at z = -radius, facing +z) and a detector plane at
+    z = detector_z facing -z.  Light from a point at the centre of curvature
+    comes back through it after one reflection, so every photon's path is
+    2 radius + detector_z / cos(angle to the axis).  Reflectivity and QE are 1."""
+    pivot = np.array([0.0, 0.0, -radius])
+    u0 = np.array([0.0, 0.0, 1.0])
+    e1 = np.array([1.0, 0.0, 0.0])
+    e2 = np.array([0.0, 1.0, 0.0])
+    seg = {"pivot": pivot[None], "u0": u0[None], "e1": e1[None], "e2": e2[None], "radius0": np.array([radius])}
+    caps = {"segment": np.array([0], np.int32), "material": np.array([MIRROR], np.int32),
+            "origin": pivot[None], "axis_a": e1[None], "axis_b": e2[None],
+            "bounds": np.array([[-300.0, 300.0, -300.0, 300.0]])}
+    half = 0.5 * n_pix * pitch
+    det = {"center": np.array([0.0, 0.0, detector_z]), "normal": np.array([0.0, 0.0, -1.0]),
+           "axis_u": np.array([1.0, 0.0, 0.0]), "axis_v": np.array([0.0, 1.0, 0.0]),
+           "half": np.array([half, half]), "pitch": pitch, "nx": n_pix, "ny": n_pix,
+           "qe_lambda": np.array([200.0, 600.0]), "qe_value": np.array([1.0, 1.0])}
+    params = np.zeros((1, 6))
+    params[0, 2] = radius
+    return {
+        "name": "T1-isochronous",
+        "materials": _materials(unit_reflectivity=True),
+        "segments": seg,
+        "params": params,
+        "caps": caps,
+        "rects": _empty_rects(),
+        "meshes": [],
+        "detector": det,
+        "box": {"lo": np.array([-3000.0, -3000.0, -3000.0]), "hi": np.array([3000.0, 3000.0, 3000.0])},
+        "max_bounces": 16,
+        "t_min": 1e-2,
+    }
+
+
 # ---------------------------------------------------------------------------
 # Sources
 # ---------------------------------------------------------------------------
+
+def gas_dispersion(n_at_400=1.0014, pole_nm=73.6, step_nm=25.0, lambda_min=LAMBDA_MIN, lambda_max=LAMBDA_MAX):
+    """A synthetic dispersion table for a fluorocarbon-like radiator gas: nodes every
+    `step_nm`, (n - 1) from a one-pole form A / (pole^-2 - lambda^-2) scaled to
+    n(400 nm) = n_at_400, rounded so that n - 1 is FP32-representable.  About
+    +-7 % variation of n - 1 across 200..600 nm."""
+    lam = np.arange(lambda_min, lambda_max + 0.5 * step_nm, step_nm)
+    shape = 1.0 / (pole_nm ** -2 - lam ** -2)
+    m = (n_at_400 - 1.0) * shape / (1.0 / (pole_nm ** -2 - 400.0 ** -2))
+    return {"lambda": lam, "index": 1.0 + f32(m)}
+
+
+def with_dispersion(src, table=None):
+    """The same source with a wavelength-dependent refractive index (default: gas_dispersion())."""
+    out = dict(src)
+    out["dispersion"] = gas_dispersion() if table is None else table
+    return out
+
 
 def point_source(origin=(0.0, 0.0, 0.0), direction=(0.0, 0.0, 1.0), beta=1.0,
                  n_radiator=N_RADIATOR, lambda_min=LAMBDA_MIN, lambda_max=LAMBDA_MAX, length=0.0):
