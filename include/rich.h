@@ -183,6 +183,29 @@ typedef struct rich_prefilter {
     int32_t materials[4];         /* mirror materials whose reflectivity enters the product */
 } rich_prefilter;
 
+/* Wavelength dependence of the radiator's refractive index (Section 3: the
+ * cone angle is set by n).  n_nodes = 0 (the default) uses the constant
+ * n_radiator.  Otherwise n(lambda) is piecewise linear through the host
+ * arrays (lambda strictly increasing, n >= 1, 1..32 nodes), clamped outside,
+ * and
+ *   - wavelengths follow the Frank-Tamm spectrum (1 - 1/(beta n)^2)/lambda^2:
+ *     the 1/lambda^2 draw (Philox block 0, word 1) is accepted with
+ *     probability w(lambda)/w_max, w = 1 - 1/(beta n)^2 and w_max its largest
+ *     value over [lambda_min, lambda_max]; its acceptance uniform is word 0
+ *     of block 0x7FFFFFFE; retry k >= 1 draws both from words 1 and 0 of
+ *     block 0x7FFFFFFE - k; after 64 rejections the last draw stands;
+ *   - the cone follows the photon's own index, cos(theta) = 1/(n(lambda) beta);
+ *   - light travels at c/n_g, n_g = n - lambda dn/dlambda (the table
+ *     segment's slope, 0 outside the table).
+ * Without a table n_g = n_radiator.  The arrays are read during the call
+ * only; a table with one index everywhere gives the plain photons. */
+typedef struct rich_dispersion {
+    int32_t n_nodes;
+    int32_t reserved;
+    const double *lambda;         /* [n_nodes] nm, host */
+    const double *index;          /* [n_nodes] refractive index, host */
+} rich_dispersion;
+
 #define RICH_SRC_TRACK    0       /* Cherenkov photons from a straight track segment (length 0: a point) */
 #define RICH_SRC_EXPLICIT 2       /* photons given one by one (Section 4.2) */
 
@@ -199,6 +222,7 @@ typedef struct rich_source {
     /* spectrum and radiator (TRACK) */
     double n_radiator, lambda_min, lambda_max;
     rich_prefilter prefilter;
+    rich_dispersion dispersion;   /* TRACK and EXPLICIT (group index for hit_time) */
 } rich_source;
 
 /* One track of a batch (32 bytes). */
@@ -218,6 +242,7 @@ typedef struct rich_batch {
     int32_t reserved;
     double n_radiator, lambda_min, lambda_max;
     rich_prefilter prefilter;
+    rich_dispersion dispersion;
 } rich_batch;
 
 /* --------------------------------------------------------------- outputs ---- */
@@ -239,6 +264,9 @@ typedef struct rich_outputs {
     rich_hit *hit_list;           /* [capacity] DETECTED photons, in no particular order */
     uint64_t hit_list_capacity;
     unsigned long long *hit_count;    /* [1] accumulated; may exceed capacity (flag raised) */
+    float *hit_time;              /* [N] ns: emission s/(beta c) after the track start (0 for explicit
+                                     photons) plus path length x n_g / c to the detector hit; NaN
+                                     unless DETECTED / QE_REJECTED */
 } rich_outputs;
 
 /* Launch shape of the persistent batch kernel. */
@@ -300,6 +328,15 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
                                    const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
                                    hipStream_t stream);
+
+/* Cherenkov photons emitted per mm of track at velocity beta (Frank-Tamm):
+ * 2 pi alpha times the integral over [lambda_min, lambda_max] of
+ * (1 - 1/(beta n(lambda))^2)^+ / lambda^2, lambda in mm, alpha the fine
+ * structure constant; n from `dispersion` (NULL or 0 nodes: n_radiator).
+ * The expected photon count of a track of length L is L times this; the
+ * caller draws the counts (offsets of a batch).  Host only, synchronous. */
+rich_status rich_cherenkov_yield(const rich_dispersion *dispersion, double n_radiator, double beta,
+                                 double lambda_min, double lambda_max, double *photons_per_mm);
 
 /* Synchronise the stream, return the device flags raised since the last call
  * (RICH_FLAG_*) and clear them.  Returns RICH_EOVERFLOW when any is set. */

@@ -47,6 +47,52 @@ rich_status check_spectrum(double n, double lmin, double lmax) {
     return RICH_OK;
 }
 
+double table_at(int n, const double *x, const double *y, double l) {
+    if (l <= x[0]) return y[0];
+    if (l >= x[n - 1]) return y[n - 1];
+    int i = 0;
+    while (i + 1 < n - 1 && l >= x[i + 1]) ++i;
+    return y[i] + (y[i + 1] - y[i]) * (l - x[i]) / (x[i + 1] - x[i]);
+}
+
+rich_status check_dispersion(const rich_dispersion &dp) {
+    if (dp.n_nodes < 0 || dp.n_nodes > kMaxTable) return set_error(RICH_EINVAL, "dispersion: 0..%d nodes", kMaxTable);
+    if (dp.n_nodes == 0) return RICH_OK;
+    if (!dp.lambda || !dp.index) return set_error(RICH_EINVAL, "dispersion: lambda and index arrays needed");
+    for (int k = 0; k < dp.n_nodes; ++k) {
+        if (!std::isfinite(dp.lambda[k]) || !std::isfinite(dp.index[k]) || !(dp.index[k] >= 1.0))
+            return set_error(RICH_EINVAL, "dispersion: finite wavelengths and indices >= 1");
+        if (k > 0 && !(dp.lambda[k] > dp.lambda[k - 1]))
+            return set_error(RICH_EINVAL, "dispersion: wavelengths must increase");
+    }
+    return RICH_OK;
+}
+
+// Largest index over [lmin, lmax]: n is piecewise linear, so at an end or a node.
+double dispersion_nmax(const rich_dispersion &dp, double lmin, double lmax) {
+    double m = std::max(table_at(dp.n_nodes, dp.lambda, dp.index, lmin), table_at(dp.n_nodes, dp.lambda, dp.index, lmax));
+    for (int k = 0; k < dp.n_nodes; ++k)
+        if (dp.lambda[k] > lmin && dp.lambda[k] < lmax) m = std::max(m, dp.index[k]);
+    return m;
+}
+
+// Device copy of a dispersion table: nodes, n - 1 (kept apart from the 1 so
+// FP32 holds it to ~1e-10) and the segment slopes.
+rich_status set_dispersion(const rich_dispersion &dp, double lmin, double lmax, DevSource &ds) {
+    rich_status st = check_dispersion(dp);
+    if (st) return st;
+    ds.n_disp = dp.n_nodes;
+    for (int k = 0; k < dp.n_nodes; ++k) {
+        ds.disp_x[k] = (float)dp.lambda[k];
+        ds.disp_m[k] = (float)(dp.index[k] - 1.0);
+        ds.disp_s[k] = k + 1 < dp.n_nodes
+                           ? (float)((dp.index[k + 1] - dp.index[k]) / (dp.lambda[k + 1] - dp.lambda[k]))
+                           : 0.0f;
+    }
+    ds.disp_nmax = dp.n_nodes > 0 ? dispersion_nmax(dp, lmin, lmax) : 0.0;
+    return RICH_OK;
+}
+
 // Host FP64 set-up of a single track source: unit direction, its orthonormal
 // basis (Duff et al., JCGT 2017), the Cherenkov cone cos = 1/(n beta) and the
 // wavelength inverse-CDF constants, rounded once to FP32.
@@ -59,6 +105,9 @@ rich_status make_track_source(const rich_source *src, DevSource &ds) {
         ds.ex_o = src->dev_o;
         ds.ex_d = src->dev_d;
         ds.ex_l = src->dev_lambda;
+        // group index for arrival times: n_radiator when it is a refractive index, else vacuum
+        ds.ng_const = (std::isfinite(src->n_radiator) && src->n_radiator >= 1.0) ? (float)src->n_radiator : 1.0f;
+        if (src->dispersion.n_nodes > 0) return set_dispersion(src->dispersion, 0.0, 0.0, ds);
         return RICH_OK;
     }
     if (src->kind != RICH_SRC_TRACK) return set_error(RICH_EINVAL, "unknown source kind %d", src->kind);
@@ -69,6 +118,12 @@ rich_status make_track_source(const rich_source *src, DevSource &ds) {
         if (!std::isfinite(o[a]) || !std::isfinite(t[a])) return set_error(RICH_EINVAL, "track origin/direction not finite");
     if (!std::isfinite(src->length) || src->length < 0) return set_error(RICH_EINVAL, "track length must be >= 0");
     double nb = src->n_radiator * src->beta;
+    if (src->dispersion.n_nodes > 0) {
+        // with dispersion the largest index over the band must be above threshold
+        st = set_dispersion(src->dispersion, src->lambda_min, src->lambda_max, ds);
+        if (st) return st;
+        nb = ds.disp_nmax * src->beta;
+    }
     if (!(nb > 1.0) || !std::isfinite(nb)) return set_error(RICH_EINVAL, "n*beta = %g: no Cherenkov light", nb);
     double len = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     if (!(len > 0)) return set_error(RICH_EINVAL, "track direction is zero");
@@ -87,6 +142,8 @@ rich_status make_track_source(const rich_source *src, DevSource &ds) {
         ds.E2[q] = (float)E2[q];
     }
     ds.length = (float)src->length;
+    ds.beta = (float)src->beta;
+    ds.ng_const = (float)src->n_radiator;
     ds.cos_t = (float)c;
     ds.sin_t = (float)std::sqrt((1.0 - c) * (1.0 + c));
     ds.inv_lmin = (float)(1.0 / src->lambda_min);
@@ -120,8 +177,12 @@ rich_status make_batch_source(const rich_batch *b, DevSource &ds) {
     ds.offsets = b->dev_offsets;
     ds.n_tracks = b->n_tracks;
     ds.n_radiator = b->n_radiator;
+    ds.ng_const = (float)b->n_radiator;
     ds.inv_lmin = (float)(1.0 / b->lambda_min);
     ds.inv_span = (float)(1.0 / b->lambda_min - 1.0 / b->lambda_max);
+    // per-track velocities live on the device: the tracks must be above
+    // threshold (n_max beta > 1), which the host cannot check here
+    if (b->dispersion.n_nodes > 0) return set_dispersion(b->dispersion, b->lambda_min, b->lambda_max, ds);
     return RICH_OK;
 }
 
@@ -138,6 +199,7 @@ DevOutputs make_outputs(const rich_outputs *o) {
     d.hit_list = o->hit_list;
     d.hit_count = o->hit_count;
     d.hit_capacity = o->hit_list_capacity;
+    d.hit_time = o->hit_time;
     return d;
 }
 
@@ -407,17 +469,15 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
             }
         }
         DevOutputs dout = make_outputs(out);
-        char key[512];
-        std::snprintf(key, sizeof key, "%p/%p/%d/%llu/%llu/%p/%p/%p/%p/%p/%p/%p/%p/%llu/%d/%d/%d",
-                      (const void *)batch->dev_tracks, (const void *)batch->dev_offsets, batch->n_tracks,
-                      (unsigned long long)n_photons, (unsigned long long)seed, (void *)dout.fate, (void *)dout.pixel,
-                      (void *)dout.hit_xyz, (void *)dout.hit_uv, (void *)dout.histogram, (void *)dout.fate_counts,
-                      dout.hit_list, (void *)dout.hit_count, (unsigned long long)dout.hit_capacity, t.block, t.chunk,
-                      t.blocks_per_cu);
-        std::string k2 = std::string(key) + "/" + std::to_string(batch->n_radiator) + "/" +
-                         std::to_string(batch->lambda_min) + "/" + std::to_string(batch->lambda_max) + "/pf" +
-                         std::to_string(ds.prefilter) + ":" + std::to_string(ds.pf_n);
-        for (int k = 0; k < ds.pf_n; ++k) k2 += "," + std::to_string(ds.pf_mats[k]);
+        // the graph is reused while every launch argument is the same: compare
+        // their bytes (both structs are zero-filled before they are set)
+        std::string k2;
+        auto put = [&](const void *p, size_t bytes) { k2.append(reinterpret_cast<const char *>(p), bytes); };
+        put(&ds, sizeof ds);
+        put(&dout, sizeof dout);
+        put(&n_photons, sizeof n_photons);
+        put(&seed, sizeof seed);
+        put(&t, sizeof t);
         if (!s->graph_exec || s->graph_key != k2) {
             if (s->graph_exec) {
                 (void)hipGraphExecDestroy(s->graph_exec);
@@ -486,6 +546,77 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
     AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, s->d_partials, dev_grad_params, dev_loss,
                   n_par};
     RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, n_blocks, stream));
+    return RICH_OK;
+}
+
+// Gauss-Legendre rule on [-1, 1]: nodes are the roots of P_n, found by Newton
+// iteration from Chebyshev-like starting points; w = 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, double *x, double *w) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;               // P_0, P_1, then the three-term recurrence
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+rich_status rich_cherenkov_yield(const rich_dispersion *dispersion, double n_radiator, double beta,
+                                 double lambda_min, double lambda_max, double *photons_per_mm) {
+    if (!photons_per_mm) return set_error(RICH_EINVAL, "photons_per_mm is NULL");
+    if (!(beta > 0) || !std::isfinite(beta)) return set_error(RICH_EINVAL, "beta must be finite and > 0");
+    rich_dispersion none{0, 0, nullptr, nullptr};
+    const rich_dispersion &dp = dispersion ? *dispersion : none;
+    rich_status st = check_dispersion(dp);
+    if (st) return st;
+    if (dp.n_nodes == 0 && (st = check_spectrum(n_radiator, lambda_min, lambda_max))) return st;
+    if (!(lambda_min > 0) || !(lambda_max > lambda_min) || !std::isfinite(lambda_max))
+        return set_error(RICH_EINVAL, "need 0 < lambda_min < lambda_max");
+    auto index = [&](double l) { return dp.n_nodes > 0 ? table_at(dp.n_nodes, dp.lambda, dp.index, l) : n_radiator; };
+    auto weight = [&](double l) {
+        double n = index(l), w = 1.0 - 1.0 / (beta * beta * n * n);
+        return w > 0.0 ? w / (l * l) : 0.0;
+    };
+    // pieces on which n is linear: the band split at the table nodes, each
+    // split again where n beta crosses 1 (the integrand has a kink there)
+    std::vector<double> cuts{lambda_min};
+    for (int k = 0; k < dp.n_nodes; ++k)
+        if (dp.lambda[k] > lambda_min && dp.lambda[k] < lambda_max) cuts.push_back(dp.lambda[k]);
+    cuts.push_back(lambda_max);
+    constexpr int kPoints = 16;
+    double gx[kPoints], gw[kPoints];
+    gauss_legendre(kPoints, gx, gw);
+    double integral = 0.0;   // of w / lambda^2 over lambda in nm
+    for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+        double lo = cuts[q], hi = cuts[q + 1];
+        double nlo = index(lo), nhi = index(hi);
+        double pieces[3] = {lo, hi, hi};
+        int np = 2;
+        if ((nlo * beta > 1.0) != (nhi * beta > 1.0)) {
+            pieces[1] = lo + (1.0 / beta - nlo) / (nhi - nlo) * (hi - lo);
+            np = 3;
+        }
+        for (int p = 0; p + 1 < np; ++p) {
+            double a = pieces[p], b = pieces[p + 1], half = 0.5 * (b - a), mid = 0.5 * (a + b);
+            double sum = 0.0;
+            for (int i = 0; i < kPoints; ++i) sum += gw[i] * weight(mid + half * gx[i]);
+            integral += half * sum;
+        }
+    }
+    const double alpha = 1.0 / 137.035999084, pi = 3.14159265358979323846;
+    // lambda in mm: the nm integral times 1e6
+    *photons_per_mm = 2.0 * pi * alpha * 1e6 * integral;
     return RICH_OK;
 }
 

@@ -231,6 +231,7 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
             p[0] = on_det ? end.u : __builtin_nanf("");
             p[1] = on_det ? end.v : __builtin_nanf("");
         }
+        if (out.hit_time) out.hit_time[i] = on_det ? end.time : __builtin_nanf("");
         if (out.histogram && end.fate == kDetected) atomicAdd(out.histogram + end.pixel, 1u);
     }
     if (out.hit_list) {

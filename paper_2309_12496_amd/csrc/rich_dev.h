@@ -177,7 +177,18 @@ struct DevSource {
     int32_t prefilter;
     int32_t pf_n;
     int32_t pf_mats[4];
+    // radiator dispersion (n_disp = 0: constant index): nodes, n - 1 and the
+    // segment slopes dn/dlambda; the largest index over the band (FP64 host)
+    int32_t n_disp;
+    float disp_x[kMaxTable], disp_m[kMaxTable], disp_s[kMaxTable];
+    double disp_nmax;
+    float ng_const;     // group index without a table
+    float beta;         // track: particle velocity / c
 };
+
+constexpr uint32_t kDispBlock = 0x7FFFFFFEu;   // wavelength retries use blocks kDispBlock - k
+constexpr int kDispMaxTries = 64;
+constexpr float kInvC = 1.0f / 299.792458f;    // ns per mm in vacuum
 
 constexpr uint32_t kPrefilterBlock = 0x7FFFFFFFu;   // Philox block of the pre-filter draw
 
@@ -191,6 +202,7 @@ struct DevOutputs {
     void *hit_list;             // rich_hit[]
     unsigned long long *hit_count;
     uint64_t hit_capacity;
+    float *hit_time;
 };
 
 }  // namespace rich

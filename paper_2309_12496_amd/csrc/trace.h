@@ -82,7 +82,32 @@ struct Photon {
     V3 o, d;
     float lambda;
     float u_qe;
+    float t0;       // emission time after the track start (ns)
+    float ng_c;     // group index / c (ns per mm)
 };
+
+// n(lambda) - 1 and the table slope dn/dlambda at l (slope 0 outside the
+// table), by the same uniform scan as lerp_table.
+__device__ __forceinline__ float disp_lookup(const DevSource &src, float l, float &slope) {
+    const int n = src.n_disp;
+    float v = l <= src.disp_x[0] ? src.disp_m[0] : src.disp_m[n - 1];
+    slope = 0.0f;
+    for (int j = 0; j + 1 < n; ++j) {
+        float xa = src.disp_x[j];
+        if (l >= xa && l < src.disp_x[j + 1]) {
+            v = fmaf(src.disp_s[j], l - xa, src.disp_m[j]);
+            slope = src.disp_s[j];
+        }
+    }
+    return v;
+}
+
+// Frank-Tamm weight 1 - 1/(beta n)^2 (zero below threshold), FP64: n - 1 is
+// small, so the cone and the acceptance need more than FP32 carries in n.
+__device__ __forceinline__ double ft_weight(double n, double beta) {
+    double w = 1.0 - 1.0 / (beta * beta * n * n);
+    return w > 0.0 ? w : 0.0;
+}
 
 __device__ __forceinline__ int find_track(const uint64_t *off, int n_tracks, uint64_t g) {
     int lo = 0, hi = n_tracks;  // last k with off[k] <= g
@@ -110,10 +135,13 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
         ph.o = ld3(src.ex_o + 3 * i);
         ph.d = ld3(src.ex_d + 3 * i);
         ph.lambda = src.ex_l[i];
+        ph.t0 = 0.0f;
+        float slope = 0.0f, m = src.n_disp > 0 ? disp_lookup(src, ph.lambda, slope) : 0.0f;
+        ph.ng_c = (src.n_disp > 0 ? 1.0f + fmaf(-ph.lambda, slope, m) : src.ng_const) * kInvC;
         return ph;
     }
     V3 P0, T, E1, E2;
-    float L, ct, st;
+    float L, ct, st, beta;
     if (src.kind == 1) {
         int k = find_track(src.offsets, src.n_tracks, g);
         const float4 *tr = reinterpret_cast<const float4 *>(src.tracks) + 2 * k;
@@ -122,6 +150,7 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
         T = V3{a.w, b.x, b.y};
         T = rsqrtf(dot(T, T)) * T;
         L = b.z;
+        beta = b.w;
         double c = 1.0 / (src.n_radiator * (double)b.w);
         ct = (float)c;
         st = (float)sqrt((1.0 - c) * (1.0 + c));
@@ -134,13 +163,35 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
         L = src.length;
         ct = src.cos_t;
         st = src.sin_t;
+        beta = src.beta;
     }
     ph.lambda = rcp(fmaf(-u24(w.y), src.inv_span, src.inv_lmin));
+    ph.ng_c = src.ng_const * kInvC;
+    if (src.n_disp > 0) {
+        // Frank-Tamm spectrum with dispersion: accept the 1/lambda^2 draw with
+        // probability w(lambda)/w_max, else draw again from the next block
+        const double b2 = (double)beta;
+        const double wmax = ft_weight(src.disp_nmax, b2);
+        float slope = 0.0f, m = 0.0f;
+        for (int k = 0; k < kDispMaxTries; ++k) {
+            uint4 r = photon_block(seed, g, kDispBlock - (uint32_t)k);
+            if (k > 0) ph.lambda = rcp(fmaf(-u24(r.y), src.inv_span, src.inv_lmin));
+            m = disp_lookup(src, ph.lambda, slope);
+            if ((double)u24(r.x) < ft_weight(1.0 + (double)m, b2) / wmax) break;
+        }
+        // the cone at the photon's own index
+        double c = 1.0 / ((1.0 + (double)m) * b2);
+        ct = (float)c;
+        st = (float)sqrt((1.0 - c) * (1.0 + c));
+        ph.ng_c = (1.0f + fmaf(-ph.lambda, slope, m)) * kInvC;
+    }
     float sp, cp;
     sincospif(2.0f * u24(w.x), &sp, &cp);
     V3 d = fma3(ct, T, st * fma3(cp, E1, sp * E2));
     ph.d = rsqrtf(dot(d, d)) * d;
-    ph.o = fma3(u24(w.z) * L, T, P0);
+    const float s = u24(w.z) * L;
+    ph.o = fma3(s, T, P0);
+    ph.t0 = s / beta * kInvC;
     return ph;
 }
 
@@ -484,6 +535,7 @@ struct PathEnd {
     int pixel;
     V3 P;
     float u, v;
+    float time;     // arrival time at the detector hit (ns)
 };
 
 // Receives every reflection and the detector hit; the forward kernels ignore them.
@@ -532,6 +584,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
     end.pixel = -1;
     uint4 blk = make_uint4(0, 0, 0, 0);
     int have = -1;
+    float travelled = 0.0f;     // path length before the current segment (mm)
     for (int b = 0; b < S.max_bounces; ++b) {
         Hit h;
         closest_hit(S, det, o, d, h, stk, stride);
@@ -555,6 +608,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             end.P = fma3(h.t, d, o);
             end.u = u;
             end.v = v;
+            end.time = fmaf(travelled + h.t, ph.ng_c, ph.t0);
             rec.detect(b, o, d, h.t);
             if (efficiencies) {
                 float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
@@ -590,6 +644,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             }
         }
         rec.reflect(b, h, o, d, P, n);
+        travelled += h.t;
         V3 dr = fma3(-2.0f * dot(d, n), n, d);
         d = rsqrtf(dot(dr, dr)) * dr;
         o = P;

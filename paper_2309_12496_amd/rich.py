@@ -89,24 +89,29 @@ class rich_prefilter(C.Structure):
     _fields_ = [("enabled", C.c_int32), ("n_materials", C.c_int32), ("materials", C.c_int32 * 4)]
 
 
+class rich_dispersion(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("reserved", C.c_int32), ("lambda_", C.POINTER(C.c_double)),
+                ("index", C.POINTER(C.c_double))]
+
+
 class rich_source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("origin", _d3), ("direction", _d3),
                 ("length", C.c_double), ("beta", C.c_double),
                 ("dev_o", C.c_void_p), ("dev_d", C.c_void_p), ("dev_lambda", C.c_void_p),
                 ("n_radiator", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
-                ("prefilter", rich_prefilter)]
+                ("prefilter", rich_prefilter), ("dispersion", rich_dispersion)]
 
 
 class rich_batch(C.Structure):
     _fields_ = [("dev_tracks", C.c_void_p), ("dev_offsets", C.c_void_p), ("n_tracks", C.c_int32),
                 ("reserved", C.c_int32), ("n_radiator", C.c_double), ("lambda_min", C.c_double),
-                ("lambda_max", C.c_double), ("prefilter", rich_prefilter)]
+                ("lambda_max", C.c_double), ("prefilter", rich_prefilter), ("dispersion", rich_dispersion)]
 
 
 class rich_outputs(C.Structure):
     _fields_ = [("fate", C.c_void_p), ("pixel", C.c_void_p), ("hit_xyz", C.c_void_p), ("hit_uv", C.c_void_p),
                 ("histogram", C.c_void_p), ("fate_counts", C.c_void_p), ("hit_list", C.c_void_p),
-                ("hit_list_capacity", C.c_uint64), ("hit_count", C.c_void_p)]
+                ("hit_list_capacity", C.c_uint64), ("hit_count", C.c_void_p), ("hit_time", C.c_void_p)]
 
 
 class rich_tuning(C.Structure):
@@ -126,15 +131,18 @@ _L.rich_propagate_adjoint.argtypes = [C.c_void_p, C.POINTER(rich_source), C.POIN
                                       C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
 _L.rich_get_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
+_L.rich_cherenkov_yield.argtypes = [C.POINTER(rich_dispersion), C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.POINTER(C.c_double)]
 _L.rich_last_error.restype = C.c_char_p
 _L.rich_version.restype = C.c_char_p
 for _f in ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params", "rich_propagate",
-           "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_get_status"):
+           "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_get_status",
+           "rich_cherenkov_yield"):
     getattr(_L, _f).restype = C.c_int32
 
 EXPORTED = ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params",
             "rich_propagate", "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint",
-            "rich_get_status", "rich_last_error", "rich_version")
+            "rich_get_status", "rich_cherenkov_yield", "rich_last_error", "rich_version")
 
 
 def _check(code):
@@ -205,6 +213,13 @@ def rich_propagate_adjoint(handle, source, batch, n_photons, seed, first_photon_
                                      int(first_photon_id), _ptr(dev_grad_uv), _ptr(dev_targets), _ptr(dev_mask),
                                      _ptr(dev_residual_cut), _ptr(dev_grad_params), _ptr(dev_loss),
                                      _stream(stream)))
+
+
+def rich_cherenkov_yield(dispersion, n_radiator, beta, lambda_min, lambda_max):
+    out = C.c_double()
+    _check(_L.rich_cherenkov_yield(None if dispersion is None else C.byref(dispersion), float(n_radiator),
+                                   float(beta), float(lambda_min), float(lambda_max), C.byref(out)))
+    return out.value
 
 
 def rich_get_status(handle, stream=None):
@@ -356,11 +371,34 @@ def _set_prefilter(pf_struct, mats):
         pf_struct.materials[k] = int(m)
 
 
+def _set_dispersion(d_struct, table, keep):
+    if table is None:
+        return
+    x = np.ascontiguousarray(table["lambda"], np.float64)
+    n = np.ascontiguousarray(table["index"], np.float64)
+    if x.shape != n.shape:
+        raise ValueError("dispersion: lambda and index differ in length")
+    keep += [x, n]
+    d_struct.n_nodes = len(x)
+    d_struct.lambda_ = x.ctypes.data_as(C.POINTER(C.c_double))
+    d_struct.index = n.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def cherenkov_yield(src, beta):
+    """Cherenkov photons per mm of track at velocity beta for a source dict's radiator."""
+    keep = []
+    d = rich_dispersion()
+    _set_dispersion(d, src.get("dispersion"), keep)
+    return rich_cherenkov_yield(d, src.get("n_radiator", 1.0), beta, src.get("lambda_min", 200.0),
+                                src.get("lambda_max", 600.0))
+
+
 def make_source(src, device="cuda"):
     """rich_source for a 'track' or 'explicit' source dict; returns (source, keepalive)."""
     s = rich_source()
     keep = []
     _set_prefilter(s.prefilter, src.get("prefilter"))
+    _set_dispersion(s.dispersion, src.get("dispersion"), keep)
     s.n_radiator = float(src.get("n_radiator", 1.0))
     s.lambda_min = float(src.get("lambda_min", 200.0))
     s.lambda_max = float(src.get("lambda_max", 600.0))
@@ -394,7 +432,9 @@ def make_batch(src, device="cuda"):
     b.lambda_min = float(src["lambda_min"])
     b.lambda_max = float(src["lambda_max"])
     _set_prefilter(b.prefilter, src.get("prefilter"))
-    return b, [tracks, offsets], int(np.asarray(src["offsets"])[-1])
+    keep = [tracks, offsets]
+    _set_dispersion(b.dispersion, src.get("dispersion"), keep)
+    return b, keep, int(np.asarray(src["offsets"])[-1])
 
 
 def alloc_outputs(scene, n, device="cuda", per_photon=True, hit_list_capacity=0):
@@ -405,6 +445,7 @@ def alloc_outputs(scene, n, device="cuda", per_photon=True, hit_list_capacity=0)
         t["pixel"] = torch.empty(n, dtype=torch.int32, device=device)
         t["hit_xyz"] = torch.empty((n, 3), dtype=torch.float32, device=device)
         t["hit_uv"] = torch.empty((n, 2), dtype=torch.float32, device=device)
+        t["hit_time"] = torch.empty(n, dtype=torch.float32, device=device)
     t["histogram"] = torch.zeros(scene.nx * scene.ny, dtype=torch.int32, device=device)
     t["fate_counts"] = torch.zeros(N_FATES, dtype=torch.int64, device=device)
     if hit_list_capacity:
@@ -415,7 +456,7 @@ def alloc_outputs(scene, n, device="cuda", per_photon=True, hit_list_capacity=0)
 
 def outputs_struct(t):
     o = rich_outputs()
-    for k in ("fate", "pixel", "hit_xyz", "hit_uv", "histogram", "fate_counts", "hit_list", "hit_count"):
+    for k in ("fate", "pixel", "hit_xyz", "hit_uv", "histogram", "fate_counts", "hit_list", "hit_count", "hit_time"):
         if k in t and t[k] is not None:
             setattr(o, k, t[k].data_ptr())
     if "hit_list" in t and t["hit_list"] is not None:

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from conftest import ROOT
+from paper_2309_12496_amd import inputs as I
 
 HEADER = os.path.join(ROOT, "include", "rich.h")
 LIB = os.path.join(ROOT, "paper_2309_12496_amd", "librich.so")
@@ -82,3 +83,18 @@ def test_scene_validation_rejects_bad_input_before_any_device_work(lib, breaker)
     assert code == R.RICH_EINVAL
     assert not out.value
     assert R.rich_last_error()
+
+
+def test_cherenkov_yield_matches_oracle(orc):
+    """rich_cherenkov_yield (host Gauss-Legendre) against the oracle's composite Simpson, and its checks."""
+    from paper_2309_12496_amd import rich as R
+    src = I.point_source()
+    disp = I.with_dispersion(src)
+    for s in (src, disp):
+        for beta in (1.0, 0.99995, 1 / 1.00146):
+            assert R.cherenkov_yield(s, beta) == pytest.approx(orc.cherenkov_yield(s, beta), rel=1e-10, abs=1e-15)
+    assert R.cherenkov_yield(src, 0.99) == 0.0
+    with pytest.raises(R.RichError):
+        R.rich_cherenkov_yield(None, 1.0014, -1.0, 200.0, 600.0)
+    with pytest.raises(R.RichError):
+        R.cherenkov_yield(I.with_dispersion(src, {"lambda": [300.0, 200.0], "index": [1.001, 1.001]}), 1.0)

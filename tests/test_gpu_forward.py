@@ -97,7 +97,7 @@ def test_c2_meshed_subset_at_full_size(R, orc, c2):
     out = R.propagate(gs, cfg["source"], n, cfg["seed"])
     ids = np.arange(0, n, 100, dtype=np.uint64)
     ref = orc.propagate(os_, cfg["source"], 0, cfg["seed"], ids=ids)
-    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv")}
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
     rep = compare(sub, ref, label="C2 subset")
     _hist_counts_consistent(out, gs.nx, gs.ny)
     assert gs.status() == 0
@@ -204,7 +204,7 @@ def test_c3_batch_subset(R, orc):
     n = cfg["n_photons"]
     ids = np.arange(0, n, 41, dtype=np.uint64)
     ref = orc.propagate(cfg["scene"], cfg["source"], 0, cfg["seed"], ids=ids)
-    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv")}
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
     compare(sub, ref, label="C3 subset")
     _hist_counts_consistent(out, gs.nx, gs.ny)
     assert gs.status() == 0
@@ -265,7 +265,7 @@ def test_prefilter_batch_and_validation(R, orc):
     out = R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(128, 128, 4))
     ids = np.arange(0, cfg["n_photons"], 97, dtype=np.uint64)
     ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
-    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv")}
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
     compare(sub, ref, label="prefilter batch")
     bad = I.with_prefilter(I.point_source(), mirror_materials=(I.ABSORBER,))
     s, keep = R.make_source(bad)

@@ -38,7 +38,7 @@ def test_c5_batched_forward_subset(R, c5):
     assert info["n_triangles"] == 2009708 and info["n_instances"] == 34
     out = R.propagate_batch(gs, cfg["source"], cfg["seed"], tune=R.tuning(256, 256, 4))
     idx = torch.as_tensor(ids.astype(np.int64), device="cuda")
-    sub = {k: out[k][idx] for k in ("fate", "pixel", "hit_xyz", "hit_uv")}
+    sub = {k: out[k][idx] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
     ref = O.propagate(osc, cfg["source"], 0, cfg["seed"], ids=ids)
     rep = compare(sub, ref, label="C5 subset")
     counts = to_np(out["fate_counts"])

@@ -1,0 +1,113 @@
+"""GPU parity of the generation physics: dispersive radiator, arrival times, explicit photons."""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_2309_12496_amd import inputs as I
+from parity import TIME_TOL_NS, compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+C_MM_NS = 299.792458
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2309_12496_amd import rich
+    return rich
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    return oracle
+
+
+def test_dispersive_point_source_all_photons(R, orc):
+    """C1 geometry, gas dispersion table: every photon against the oracle (wavelength accept-reject,
+    cone at n(lambda), group-index arrival times)."""
+    cfg = I.config(1)
+    src = I.with_dispersion(cfg["source"])
+    gs = R.Scene(cfg["scene"])
+    out = R.propagate(gs, src, 100_000, cfg["seed"])
+    ref = orc.propagate(cfg["scene"], src, 100_000, cfg["seed"])
+    rep = compare(out, ref, label="C1 dispersive")
+    print(rep)
+
+
+def test_dispersive_batch_subset(R, orc):
+    cfg = I.config(3)
+    src = I.with_dispersion(cfg["source"])
+    gs = R.Scene(cfg["scene"])
+    out = R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(256, 256, 4))
+    ids = np.arange(0, cfg["n_photons"], 97, dtype=np.uint64)
+    ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    compare(sub, ref, label="C3 dispersive subset")
+
+
+def test_constant_table_is_the_plain_source(R):
+    """A table with one index everywhere launches the plain photons: the same wavelengths and fates;
+    directions differ only by the FP32 rounding of n - 1 (5e-11 in n), far below the hit tolerance."""
+    cfg = I.config(1)
+    gs = R.Scene(cfg["scene"])
+    flat = {"lambda": np.array([200.0, 400.0, 600.0]), "index": np.full(3, I.N_RADIATOR)}
+    a = R.propagate(gs, cfg["source"], 50_000, cfg["seed"])
+    b = R.propagate(gs, I.with_dispersion(cfg["source"], flat), 50_000, cfg["seed"])
+    for k in ("fate", "pixel"):
+        assert np.array_equal(to_np(a[k]), to_np(b[k])), k
+    assert np.nanmax(np.abs(to_np(a["hit_xyz"]) - to_np(b["hit_xyz"]))) < 1e-3
+    assert np.nanmax(np.abs(to_np(a["hit_time"]) - to_np(b["hit_time"]))) < 1e-5
+    assert np.array_equal(np.isnan(to_np(a["hit_time"])), np.isnan(to_np(b["hit_time"])))
+
+
+def test_isochronous_arrival_times(R):
+    """Source at the mirror's centre of curvature: t = (2R + z_det / cos theta) n / c for every photon."""
+    scene = I.scene_t1()
+    src = I.point_source(direction=(0.0, 0.0, -1.0))
+    gs = R.Scene(scene)
+    out = R.propagate(gs, src, 100_000, 5)
+    fate = to_np(out["fate"])
+    assert np.all(fate == R.DETECTED)
+    n = src["n_radiator"]
+    t_ref = (2 * 2000.0 + 100.0 * n) * n / C_MM_NS
+    t = to_np(out["hit_time"]).astype(np.float64)
+    assert np.abs(t - t_ref).max() < TIME_TOL_NS
+    xyz = to_np(out["hit_xyz"]).astype(np.float64)
+    r = np.hypot(xyz[:, 0], xyz[:, 1])
+    assert np.abs(r - 100.0 * math.tan(math.acos(1.0 / n))).max() < 5e-3
+
+
+def test_explicit_photons_with_times(R, orc):
+    """Explicit (o, d, lambda) arrays (Section 4.2): arrival times start at 0 and use n_radiator."""
+    cfg = I.config(1)
+    n = 100_000
+    o, d, lam = orc.generate(cfg["source"], n, 21)
+    ex = I.explicit_source(o, d, lam) | {"n_radiator": I.N_RADIATOR}
+    gs = R.Scene(cfg["scene"])
+    out = R.propagate(gs, ex, n, 21)
+    ref = orc.propagate(cfg["scene"], ex, n, 21)
+    print(compare(out, ref, label="explicit"))
+
+
+def test_dispersion_validation(R):
+    cfg = I.config(1)
+    gs = R.Scene(cfg["scene"])
+    bad_tables = [
+        {"lambda": np.array([300.0, 200.0]), "index": np.array([1.001, 1.001])},      # not increasing
+        {"lambda": np.array([200.0, 600.0]), "index": np.array([0.9, 1.001])},        # index below 1
+        {"lambda": np.linspace(200, 600, 33), "index": np.full(33, 1.001)},           # too many nodes
+        {"lambda": np.array([200.0, 600.0]), "index": np.array([1.0001, 1.0001])},    # below threshold at beta 0.999
+    ]
+    for k, tab in enumerate(bad_tables):
+        src = I.with_dispersion(I.point_source(beta=0.999 if k == 3 else 1.0), tab)
+        s, keep = R.make_source(src)
+        t, o = R.alloc_outputs(gs, 10)
+        with pytest.raises(R.RichError) as e:
+            R.rich_propagate(gs.handle, s, 10, 1, 0, o)
+        assert e.value.code == R.RICH_EINVAL, k
