@@ -101,26 +101,38 @@ def cpu_baseline(cfg, target_seconds):
     res = O.propagate(sc, cfg["source"], n, cfg["seed"], threads=threads)
     dt = time.perf_counter() - t0
     assert int(np.bincount(res["fate"], minlength=7).sum()) == n
+    # one thread, a quarter of the time budget
+    n1 = int(max(2000, min(n, rate / threads * target_seconds / 4)))
+    t0 = time.perf_counter()
+    O.propagate(sc, cfg["source"], n1, cfg["seed"], threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
-            "sample": f"photon ids 0..{n - 1} of the headline workload ({dt:.1f} s on {threads} threads)"}
+            "sample": f"photon ids 0..{n - 1} of the headline workload ({dt:.1f} s on {threads} threads)",
+            "single_thread": {"value": n1 / dt1, "unit": "photons/s",
+                              "sample": f"photon ids 0..{n1 - 1} ({dt1:.1f} s on 1 thread)"}}
 
 
 def form_batched(R, I, stream, steps):
     cfg = I.config(3)
+    t0 = time.perf_counter()
     sc = R.Scene(cfg["scene"])
+    build_s = time.perf_counter() - t0
     b, keep, n = R.make_batch(cfg["source"])
     t, o = R.alloc_outputs(sc, n)
     tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])
     ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 2, stream)
     assert sc.status() == 0
     return {"workload": cfg["name"], "photons_per_step": n, "ms_per_step": ms, "photons_per_s": n / (ms * 1e-3),
-            "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu}}
+            "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu},
+            "scene_build_s": round(build_s, 3)}
 
 
 def _fwd_adjoint(R, I, cfg, stream, steps):
     """Forward (batched) plus fused-loss adjoint per step, targets from misaligned segments."""
     import torch
+    t0 = time.perf_counter()
     sc = R.Scene(cfg["scene"])
+    build_s = time.perf_counter() - t0
     b, keep, n = R.make_batch(cfg["source"])
     tune = R.tuning(256, 256, 4)
     sc.set_params(cfg["target_params"])
@@ -141,7 +153,7 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
     return {"workload": cfg["name"], "photons_per_step": n, "parameters": 6 * sc.n_segments,
             "forward_ms": s_ms, "adjoint_ms": a_ms, "ms_per_step": s_ms + a_ms,
             "photons_per_s": n / ((s_ms + a_ms) * 1e-3), "forward_photons_per_s": n / (s_ms * 1e-3),
-            "loss_mm2": float(loss), "masked_photons": int(mask.sum())}
+            "loss_mm2": float(loss), "masked_photons": int(mask.sum()), "scene_build_s": round(build_s, 3)}
 
 
 def form_align_fit(R, I, stream, steps):

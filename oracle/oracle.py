@@ -66,6 +66,27 @@ class Outputs(C.Structure):
     ]
 
 
+class Film(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("distance", C.c_double), ("fov", C.c_double),
+                ("sigma", C.c_double), ("threshold", C.c_double)]
+
+
+def film_readout(film, fate, hit_uv, image=None):
+    """Camera + film + threshold emulation (Section 4.4) of detected hits; returns (image, hits)."""
+    f = Film(int(film["width"]), int(film["height"]), float(film["distance"]), float(film["fov"]),
+             float(film["sigma"]), float(film["threshold"]))
+    fate = np.ascontiguousarray(fate, np.uint8)
+    uv = np.ascontiguousarray(np.nan_to_num(np.asarray(hit_uv, np.float64)), np.float64)
+    if image is None:
+        image = np.zeros((f.height, f.width))
+    hits = np.zeros((f.height, f.width), np.uint8)
+    rc = lib().orc_film_readout(C.byref(f), _ptr(fate, C.c_uint8), _ptr(uv, C.c_double), len(fate),
+                                _ptr(image, C.c_double), _ptr(hits, C.c_uint8))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return image, hits
+
+
 def build(force=True):
     """Compile the oracle with gcc: -O2, IEEE double arithmetic, no fast-math."""
     src = os.path.join(HERE, "rich_oracle.c")
@@ -105,6 +126,8 @@ def lib():
         L.orc_philox4x32_r.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_int,
                                        C.POINTER(C.c_uint32)]
         L.orc_cherenkov_yield.argtypes = [C.POINTER(Source), C.c_double, C.POINTER(C.c_double)]
+        L.orc_film_readout.argtypes = [C.POINTER(Film), C.POINTER(C.c_uint8), _dp, C.c_uint64, _dp,
+                                       C.POINTER(C.c_uint8)]
         _lib = L
     return _lib
 

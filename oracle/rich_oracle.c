@@ -1161,3 +1161,37 @@ int orc_cherenkov_yield(const orc_source *src, double beta, double *photons_per_
     *photons_per_mm = 2.0 * M_PI * FINE_STRUCTURE * 1e6 * integral;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Film read-out emulation (Section 4.4)                                     */
+/* ------------------------------------------------------------------------ */
+
+int orc_film_readout(const orc_film *film, const uint8_t *fate, const double *hit_uv, uint64_t n, double *image,
+                     uint8_t *hits)
+{
+    if (!film || !image || (n && (!fate || !hit_uv))) { set_err("null argument"); return -1; }
+    if (film->width < 1 || film->height < 1 || !(film->distance > 0) || !(film->fov > 0) || !(film->fov < M_PI) ||
+        !(film->sigma > 0)) {
+        set_err("bad film");
+        return -1;
+    }
+    const int W = film->width, H = film->height;
+    const double f = 0.5 * W / tan(0.5 * film->fov);
+    const double r = 4.0 * film->sigma;
+    for (uint64_t p = 0; p < n; ++p) {
+        if (fate[p] != ORC_DETECTED) continue;
+        double x = 0.5 * W + f * hit_uv[2 * p] / film->distance;
+        double y = 0.5 * H + f * hit_uv[2 * p + 1] / film->distance;
+        /* pixels with centres i + 1/2 in [x - r, x + r] */
+        int i0 = (int)ceil(x - r - 0.5), i1 = (int)floor(x + r - 0.5);
+        int j0 = (int)ceil(y - r - 0.5), j1 = (int)floor(y + r - 0.5);
+        for (int j = j0 > 0 ? j0 : 0; j <= j1 && j < H; ++j)
+            for (int i = i0 > 0 ? i0 : 0; i <= i1 && i < W; ++i) {
+                double dx = i + 0.5 - x, dy = j + 0.5 - y;
+                image[(int64_t)j * W + i] += 255.0 * exp(-(dx * dx + dy * dy) / (2.0 * film->sigma * film->sigma));
+            }
+    }
+    if (hits)
+        for (int64_t k = 0; k < (int64_t)W * H; ++k) hits[k] = fmin(image[k], 255.0) >= film->threshold;
+    return 0;
+}

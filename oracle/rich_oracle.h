@@ -116,6 +116,24 @@ typedef struct {
  * lambda in mm; n from the source's dispersion table or n_radiator. */
 int orc_cherenkov_yield(const orc_source *src, double beta, double *photons_per_mm);
 
+/* Film read-out emulation (Section 4.4: camera, film and an intensity
+ * threshold instead of recorded hits).  A pinhole camera on the detector
+ * normal through its centre, `distance` from it, with a full field of view
+ * `fov` across `width` film pixels, maps a detector hit (u, v) to film
+ * coordinates x = width/2 + f u / distance, y = height/2 + f v / distance,
+ * f = (width/2) / tan(fov/2).  Each DETECTED photon adds
+ * 255 exp(-(dx^2 + dy^2) / (2 sigma^2)) to every pixel whose centre
+ * (i + 1/2, j + 1/2) lies within 4 sigma in x and in y (dx, dy from the
+ * projected point), so a photon centred on a pixel gives that pixel 255.
+ * image[j][i] accumulates; hits[j][i] = 1 where min(image, 255) >= threshold. */
+typedef struct {
+    int32_t width, height;
+    double distance, fov, sigma, threshold;
+} orc_film;
+
+int orc_film_readout(const orc_film *film, const uint8_t *fate, const double *hit_uv, uint64_t n, double *image,
+                     uint8_t *hits);
+
 /* Philox4x32-10: ctr[4], key[2] -> out[4]. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Same with an explicit round count (rounds >= 0), for structural tests. */
