@@ -329,6 +329,34 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
                                    const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
                                    hipStream_t stream);
 
+/* Film read-out emulation (Section 4.4): the paper detects photons by
+ * imaging the detector plane with a pinhole camera onto a film and counting
+ * pixels above an intensity threshold (which spreads one photon over several
+ * pixels).  The camera sits on the detector normal through its centre,
+ * `distance` from it, with a full field of view `fov` across `width` pixels:
+ * a hit at detector coordinates (u, v) lands at film coordinates
+ *   x = width/2 + f u / distance,  y = height/2 + f v / distance,
+ *   f = (width/2) / tan(fov/2).
+ * Every DETECTED photon adds 255 exp(-(dx^2 + dy^2) / (2 sigma^2)) to each
+ * pixel (i, j) whose centre (i + 1/2, j + 1/2) lies within 4 sigma of (x, y)
+ * in x and in y, so one photon centred on a pixel gives it 255. */
+typedef struct rich_film {
+    int32_t width, height;        /* film pixels; width * height <= 2^31 */
+    double distance;              /* mm, > 0 */
+    double fov;                   /* rad, 0 < fov < pi */
+    double sigma;                 /* reconstruction filter std dev in film pixels, 0 < sigma < 64 */
+    double threshold;             /* hit when min(image, 255) >= threshold */
+} rich_film;
+
+/* Splat the DETECTED photons among dev_fate[n] / dev_hit_uv[n][2] (as
+ * written by the propagate calls) into dev_image[height][width] (FP32,
+ * accumulated: the caller zeroes it; atomic additions, so the last bits
+ * depend on their order), then, if dev_hits is not NULL, set
+ * dev_hits[height][width] to 1 where min(image, 255) >= threshold, else 0.
+ * Asynchronous on `stream`, on the current device. */
+rich_status rich_film_readout(const rich_film *film, const uint8_t *dev_fate, const float *dev_hit_uv,
+                              uint64_t n_photons, float *dev_image, uint8_t *dev_hits, hipStream_t stream);
+
 /* Cherenkov photons emitted per mm of track at velocity beta (Frank-Tamm):
  * 2 pi alpha times the integral over [lambda_min, lambda_max] of
  * (1 - 1/(beta n(lambda))^2)^+ / lambda^2, lambda in mm, alpha the fine

@@ -620,6 +620,30 @@ rich_status rich_cherenkov_yield(const rich_dispersion *dispersion, double n_rad
     return RICH_OK;
 }
 
+rich_status rich_film_readout(const rich_film *film, const uint8_t *dev_fate, const float *dev_hit_uv,
+                              uint64_t n_photons, float *dev_image, uint8_t *dev_hits, hipStream_t stream) {
+    if (!film || !dev_image) return set_error(RICH_EINVAL, "film and dev_image must not be NULL");
+    if (n_photons && (!dev_fate || !dev_hit_uv)) return set_error(RICH_EINVAL, "dev_fate and dev_hit_uv needed");
+    if (film->width < 1 || film->height < 1 || (int64_t)film->width * film->height > (1ll << 31))
+        return set_error(RICH_EINVAL, "film size out of range");
+    const double pi = 3.14159265358979323846;
+    if (!(film->distance > 0) || !std::isfinite(film->distance) || !(film->fov > 0) || !(film->fov < pi) ||
+        !(film->sigma > 0) || !(film->sigma < 64) || !std::isfinite(film->threshold))
+        return set_error(RICH_EINVAL, "film: distance > 0, 0 < fov < pi, 0 < sigma < 64, finite threshold");
+    const double f = 0.5 * film->width / std::tan(0.5 * film->fov);
+    FilmArgs a;
+    a.width = film->width;
+    a.height = film->height;
+    a.cx = (float)(0.5 * film->width);
+    a.cy = (float)(0.5 * film->height);
+    a.scale = (float)(f / film->distance);
+    a.radius = (float)(4.0 * film->sigma);
+    a.inv_2s2 = (float)(1.0 / (2.0 * film->sigma * film->sigma));
+    a.threshold = (float)film->threshold;
+    RICH_HIP(launch_film(a, dev_fate, dev_hit_uv, n_photons, dev_image, dev_hits, stream));
+    return RICH_OK;
+}
+
 rich_status rich_get_status(rich_scene *s, hipStream_t stream, uint32_t *flags) {
     if (!s) return set_error(RICH_EINVAL, "scene is NULL");
     DeviceGuard g(s->device);

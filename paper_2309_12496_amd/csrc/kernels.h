@@ -40,4 +40,15 @@ hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const Adjoint
                           uint64_t seed, int n_blocks, hipStream_t st);
 int adjoint_block_size();
 
+// Film read-out emulation: film coordinates x = cx + scale u, y = cy + scale v.
+struct FilmArgs {
+    int32_t width, height;
+    float cx, cy, scale;
+    float radius;       // 4 sigma (film pixels)
+    float inv_2s2;      // 1 / (2 sigma^2)
+    float threshold;
+};
+hipError_t launch_film(const FilmArgs &a, const uint8_t *fate, const float *uv, uint64_t n, float *image,
+                       uint8_t *hits, hipStream_t st);
+
 }  // namespace rich

@@ -434,6 +434,23 @@ def scene_t1(radius=2000.0, detector_z=100.0, n_pix=200, pitch=3.0):
     }
 
 
+def film_paper(width=1320, height=620, sigma=0.5, threshold=45.0):
+    """The paper's camera and film (Section 4.4): 1320 x 620 pixels, camera 478.69 mm in front of the
+    detector, 116.38 degree field of view, hit threshold 45 of 255.  The reconstruction filter is not
+    given; a Gaussian of sigma 0.5 pixel (radius 4 sigma) is assumed."""
+    return {"width": width, "height": height, "distance": 478.69, "fov": float(np.radians(116.38)),
+            "sigma": sigma, "threshold": threshold}
+
+
+def film_hits(n, seed, half=300.0, detected_fraction=0.8):
+    """Seeded synthetic read-out input: fates (DETECTED with the given probability, else one of the
+    other fates) and detector coordinates uniform over [-half, half]^2, FP32-representable."""
+    rng = np.random.default_rng(seed)
+    fate = np.where(rng.uniform(size=n) < detected_fraction, 0, rng.integers(1, 6, size=n)).astype(np.uint8)
+    uv = f32(rng.uniform(-half, half, size=(n, 2)))
+    return fate, uv
+
+
 # ---------------------------------------------------------------------------
 # Sources
 # ---------------------------------------------------------------------------

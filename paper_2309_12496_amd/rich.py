@@ -114,6 +114,11 @@ class rich_outputs(C.Structure):
                 ("hit_list_capacity", C.c_uint64), ("hit_count", C.c_void_p), ("hit_time", C.c_void_p)]
 
 
+class rich_film(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("distance", C.c_double), ("fov", C.c_double),
+                ("sigma", C.c_double), ("threshold", C.c_double)]
+
+
 class rich_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
 
@@ -131,18 +136,20 @@ _L.rich_propagate_adjoint.argtypes = [C.c_void_p, C.POINTER(rich_source), C.POIN
                                       C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
 _L.rich_get_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
+_L.rich_film_readout.argtypes = [C.POINTER(rich_film), C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]
 _L.rich_cherenkov_yield.argtypes = [C.POINTER(rich_dispersion), C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.POINTER(C.c_double)]
 _L.rich_last_error.restype = C.c_char_p
 _L.rich_version.restype = C.c_char_p
 for _f in ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params", "rich_propagate",
            "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_get_status",
-           "rich_cherenkov_yield"):
+           "rich_cherenkov_yield", "rich_film_readout"):
     getattr(_L, _f).restype = C.c_int32
 
 EXPORTED = ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params",
             "rich_propagate", "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint",
-            "rich_get_status", "rich_cherenkov_yield", "rich_last_error", "rich_version")
+            "rich_get_status", "rich_cherenkov_yield", "rich_film_readout", "rich_last_error", "rich_version")
 
 
 def _check(code):
@@ -220,6 +227,24 @@ def rich_cherenkov_yield(dispersion, n_radiator, beta, lambda_min, lambda_max):
     _check(_L.rich_cherenkov_yield(None if dispersion is None else C.byref(dispersion), float(n_radiator),
                                    float(beta), float(lambda_min), float(lambda_max), C.byref(out)))
     return out.value
+
+
+def rich_film_readout(film, dev_fate, dev_hit_uv, n_photons, dev_image, dev_hits, stream=None):
+    _check(_L.rich_film_readout(C.byref(film), _ptr(dev_fate), _ptr(dev_hit_uv), int(n_photons), _ptr(dev_image),
+                                _ptr(dev_hits), _stream(stream)))
+
+
+def film_readout(film, fate, hit_uv, image=None, stream=None):
+    """Camera + film + threshold emulation (Section 4.4) of detected hits on the GPU; returns (image, hits)."""
+    f = rich_film(int(film["width"]), int(film["height"]), float(film["distance"]), float(film["fov"]),
+                  float(film["sigma"]), float(film["threshold"]))
+    fate = torch.as_tensor(fate).to(device="cuda", dtype=torch.uint8).contiguous()
+    uv = torch.as_tensor(hit_uv).to(device=fate.device, dtype=torch.float32).contiguous()
+    if image is None:
+        image = torch.zeros((f.height, f.width), dtype=torch.float32, device=fate.device)
+    hits = torch.empty((f.height, f.width), dtype=torch.uint8, device=fate.device)
+    rich_film_readout(f, fate, uv, fate.numel(), image, hits, stream)
+    return image, hits
 
 
 def rich_get_status(handle, stream=None):
