@@ -201,8 +201,6 @@ struct Ray {
     V3 o, d;          // current frame (world or instance-local)
     V3 inv;           // 1/d with zeros nudged away
     V3 oi;            // o * inv
-    int kx, ky, kz;   // watertight permutation
-    float sx, sy, sz; // watertight shear
 };
 
 constexpr float kFarScale = 1.0000004f;
@@ -216,18 +214,25 @@ __device__ __forceinline__ void ray_setup(Ray &r, V3 o, V3 d) {
     r.d = d;
     r.inv = V3{safe_inv(d.x), safe_inv(d.y), safe_inv(d.z)};
     r.oi = V3{o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z};
+}
+
+// Watertight permutation and shear of a direction (Woop, Benthin, Wald).
+struct Shear {
+    int kx, ky, kz;
+    float sx, sy, sz;
+};
+__device__ __forceinline__ Shear make_shear(V3 d) {
+    Shear w;
     float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
-    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-    int kx = kz == 2 ? 0 : kz + 1;
-    int ky = kx == 2 ? 0 : kx + 1;
-    float dz = comp(d, kz);
-    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
-    r.kx = kx;
-    r.ky = ky;
-    r.kz = kz;
-    r.sz = rcp(dz);
-    r.sx = comp(d, kx) * r.sz;
-    r.sy = comp(d, ky) * r.sz;
+    w.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    w.kx = w.kz == 2 ? 0 : w.kz + 1;
+    w.ky = w.kx == 2 ? 0 : w.kx + 1;
+    float dz = comp(d, w.kz);
+    if (dz < 0.0f) { int t = w.kx; w.kx = w.ky; w.ky = t; }
+    w.sz = rcp(dz);
+    w.sx = comp(d, w.kx) * w.sz;
+    w.sy = comp(d, w.ky) * w.sz;
+    return w;
 }
 
 // Slab test of an AABB with the robust far-distance scaling of Ize (JCGT 2013).
@@ -335,13 +340,13 @@ __device__ __forceinline__ bool hit_box(const float *lo, const float *hi, const 
 }
 
 // Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013), two-sided.
-__device__ __forceinline__ bool hit_tri(const Ray &r, const float4 &a, const float4 &b, const float4 &c, float tmin,
-                                        float &t_out) {
+__device__ __forceinline__ bool hit_tri(const Ray &r, const Shear &sh, const float4 &a, const float4 &b,
+                                        const float4 &c, float tmin, float &t_out) {
     V3 A = V3{a.x, a.y, a.z} - r.o, B = V3{b.x, b.y, b.z} - r.o, C = V3{c.x, c.y, c.z} - r.o;
-    float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
-    float Ax = fmaf(-r.sx, Akz, comp(A, r.kx)), Ay = fmaf(-r.sy, Akz, comp(A, r.ky));
-    float Bx = fmaf(-r.sx, Bkz, comp(B, r.kx)), By = fmaf(-r.sy, Bkz, comp(B, r.ky));
-    float Cx = fmaf(-r.sx, Ckz, comp(C, r.kx)), Cy = fmaf(-r.sy, Ckz, comp(C, r.ky));
+    float Akz = comp(A, sh.kz), Bkz = comp(B, sh.kz), Ckz = comp(C, sh.kz);
+    float Ax = fmaf(-sh.sx, Akz, comp(A, sh.kx)), Ay = fmaf(-sh.sy, Akz, comp(A, sh.ky));
+    float Bx = fmaf(-sh.sx, Bkz, comp(B, sh.kx)), By = fmaf(-sh.sy, Bkz, comp(B, sh.ky));
+    float Cx = fmaf(-sh.sx, Ckz, comp(C, sh.kx)), Cy = fmaf(-sh.sy, Ckz, comp(C, sh.ky));
     float U = Cx * By - Cy * Bx;
     float V = Ax * Cy - Ay * Cx;
     float W = Bx * Ay - By * Ax;
@@ -353,7 +358,7 @@ __device__ __forceinline__ bool hit_tri(const Ray &r, const float4 &a, const flo
     if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
     float det = U + V + W;
     if (det == 0.0f) return false;
-    float T = U * (r.sz * Akz) + V * (r.sz * Bkz) + W * (r.sz * Ckz);
+    float T = U * (sh.sz * Akz) + V * (sh.sz * Bkz) + W * (sh.sz * Ckz);
     float t = T * rcp(det);
     if (!(t > tmin)) return false;
     t_out = t;
@@ -450,13 +455,14 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
         } else {
             uint32_t first = ref & 0x07FFFFFFu;
             uint32_t cnt = ((ref >> 27) & 7u) + 1u;
+            const Shear sh = make_shear(r.d);
             for (uint32_t q = first; q < first + cnt; ++q) {
                 const char *tb = reinterpret_cast<const char *>(S.tris) + (q << 6);
                 float4 a = *reinterpret_cast<const float4 *>(tb);
                 float4 b = *reinterpret_cast<const float4 *>(tb + 16);
                 float4 c = *reinterpret_cast<const float4 *>(tb + 32);
                 float t;
-                if (hit_tri(r, a, b, c, tmin, t)) {
+                if (hit_tri(r, sh, a, b, c, tmin, t)) {
                     uint32_t prim = S.prim_tri + __float_as_uint(a.w);
                     if (better(t, prim, h)) {
                         h.t = t;
@@ -584,7 +590,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
     end.pixel = -1;
     uint4 blk = make_uint4(0, 0, 0, 0);
     int have = -1;
-    float travelled = 0.0f;     // path length before the current segment (mm)
+    float clock = ph.t0;        // time at the start of the current segment (ns)
     for (int b = 0; b < S.max_bounces; ++b) {
         Hit h;
         closest_hit(S, det, o, d, h, stk, stride);
@@ -608,7 +614,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             end.P = fma3(h.t, d, o);
             end.u = u;
             end.v = v;
-            end.time = fmaf(travelled + h.t, ph.ng_c, ph.t0);
+            end.time = fmaf(h.t, ph.ng_c, clock);
             rec.detect(b, o, d, h.t);
             if (efficiencies) {
                 float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
@@ -644,7 +650,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
             }
         }
         rec.reflect(b, h, o, d, P, n);
-        travelled += h.t;
+        clock = fmaf(h.t, ph.ng_c, clock);
         V3 dr = fma3(-2.0f * dot(d, n), n, d);
         d = rsqrtf(dot(dr, dr)) * dr;
         o = P;
