@@ -98,3 +98,30 @@ def test_cherenkov_yield_matches_oracle(orc):
         R.rich_cherenkov_yield(None, 1.0014, -1.0, 200.0, 600.0)
     with pytest.raises(R.RichError):
         R.cherenkov_yield(I.with_dispersion(src, {"lambda": [300.0, 200.0], "index": [1.001, 1.001]}), 1.0)
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/rich.h compiles as C99 and a C program linked against librich.so runs its host-only calls."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    prog = tmp_path / "abi.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include "rich.h"\n'
+        "int main(void) {\n"
+        "    double y = 0.0;\n"
+        "    if (rich_cherenkov_yield(NULL, 1.0014, 1.0, 200.0, 600.0, &y) != RICH_OK) return 1;\n"
+        "    if (rich_cherenkov_yield(NULL, 1.0014, -1.0, 200.0, 600.0, &y) != RICH_EINVAL) return 2;\n"
+        '    printf("%.9f %s\\n", y, rich_version());\n'
+        "    return 0;\n"
+        "}\n")
+    libdir = os.path.join(ROOT, "paper_2309_12496_amd")
+    exe = tmp_path / "abi"
+    cmd = ["gcc", "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", str(prog), "-L", libdir, "-lrich", f"-Wl,-rpath,{libdir}", "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    assert r.stdout.startswith("0.427042107")
