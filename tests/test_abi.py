@@ -124,4 +124,4 @@ def test_header_is_plain_c_and_links(tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, (r.returncode, r.stderr)
-    assert r.stdout.startswith("0.427042107")
+    assert r.stdout.startswith("0.4270421")
