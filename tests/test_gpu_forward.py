@@ -65,6 +65,18 @@ def test_c1_ragged_sizes_and_offsets(R, orc, c1, n, first):
     compare(out, ref, min_agree=1.0 if n < 1000 else 0.9999, label=f"C1 n={n} first={first}")
 
 
+@pytest.mark.parametrize("first,seed", [(2**63 + 12345, None), (2**64 - 2000, None), (0, 2**64 - 1), (77, 2**32)])
+def test_extreme_ids_and_seeds(R, orc, c1, first, seed):
+    """Photon ids and seeds that use both 32-bit halves of the Philox counter and key (ids up to 2^64 - 1001)."""
+    cfg, gs, os_ = c1
+    seed = cfg["seed"] if seed is None else seed
+    n = 1000
+    out = R.propagate(gs, cfg["source"], n, seed, first_id=first)
+    ref = orc.propagate(os_, cfg["source"], n, seed, first_id=first)
+    # 1000 photons: a single explained disagreement is already 1e-3, so only explained ones are allowed
+    compare(out, ref, min_agree=0.99, label=f"C1 first={first} seed={seed}")
+
+
 def test_zero_photons_is_a_no_op(R, c1):
     import torch
     cfg, gs, _ = c1
@@ -243,6 +255,34 @@ def test_batch_graph_replay_matches_eager_single_source(R):
         sl = slice(int(offs[k]), int(offs[k + 1]))
         agree = (to_np(one["fate"]) == first["fate"][sl]) & (to_np(one["pixel"]) == first["pixel"][sl])
         assert agree.mean() >= 0.999
+
+
+def test_batch_graph_follows_every_source_field(R):
+    """The captured batch graph is reused only while all launch arguments match: switching the
+    pre-filter or the dispersion on the same batch struct and outputs must change the photons."""
+    import torch
+    cfg = I.config(3)
+    gs = R.Scene(cfg["scene"])
+    b, keep, n = R.make_batch(cfg["source"])
+    t, o = R.alloc_outputs(gs, n)
+    tune = R.tuning(256, 256, 4)
+    R.rich_propagate_batch(gs.handle, b, n, cfg["seed"], o, tune)
+    plain = to_np(t["fate"]).copy()
+    R._set_prefilter(b.prefilter, [I.MIRROR, I.MIRROR])
+    R.rich_propagate_batch(gs.handle, b, n, cfg["seed"], o, tune)
+    pre = to_np(t["fate"]).copy()
+    assert (pre == R.PREFILTERED).mean() > 0.5 and not (plain == R.PREFILTERED).any()
+    b.prefilter.enabled = 0
+    R._set_dispersion(b.dispersion, I.gas_dispersion(), keep)
+    R.rich_propagate_batch(gs.handle, b, n, cfg["seed"], o, tune)
+    disp = to_np(t["hit_time"]).copy()
+    b.dispersion.n_nodes = 0
+    R.rich_propagate_batch(gs.handle, b, n, cfg["seed"], o, tune)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(t["fate"]), plain)
+    again = to_np(t["hit_time"])
+    on = np.isfinite(again) & np.isfinite(disp)
+    assert on.sum() > 1000 and not np.array_equal(again[on], disp[on])
 
 
 def test_prefilter_mode_parity(R, orc, c2):
