@@ -234,7 +234,11 @@ typedef struct rich_track {
 } rich_track;
 
 /* Many tracks in one launch.  Track k owns global photon ids
- * [offsets[k], offsets[k+1]); offsets is the exclusive scan of the counts. */
+ * [offsets[k], offsets[k+1]); offsets is the exclusive scan of the counts
+ * (non-decreasing; the caller draws the counts, e.g. Poisson of the track
+ * length times rich_cherenkov_yield).  The tracks live on the device, so the
+ * host does not check them: a track with n beta <= 1 (n_max beta <= 1 with a
+ * dispersion table) has no cone, and its photons come out RICH_ESCAPED. */
 typedef struct rich_batch {
     const rich_track *dev_tracks; /* [n_tracks] */
     const uint64_t *dev_offsets;  /* [n_tracks + 1], offsets[0] = 0 */
