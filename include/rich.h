@@ -238,7 +238,8 @@ typedef struct rich_track {
  * (non-decreasing; the caller draws the counts, e.g. Poisson of the track
  * length times rich_cherenkov_yield).  The tracks live on the device, so the
  * host does not check them: a track with n beta <= 1 (n_max beta <= 1 with a
- * dispersion table) has no cone, and its photons come out RICH_ESCAPED. */
+ * dispersion table) has no cone, and its photons come out RICH_ESCAPED
+ * without being traced. */
 typedef struct rich_batch {
     const rich_track *dev_tracks; /* [n_tracks] */
     const uint64_t *dev_offsets;  /* [n_tracks + 1], offsets[0] = 0 */

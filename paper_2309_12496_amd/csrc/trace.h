@@ -588,6 +588,11 @@ __device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, 
     V3 o = ph.o, d = ph.d;
     end.fate = kMaxBounces;
     end.pixel = -1;
+    // a track below the Cherenkov threshold has no cone (NaN direction): no light
+    if (!(fabsf(d.x) <= 1.0f && fabsf(d.y) <= 1.0f && fabsf(d.z) <= 1.0f)) {
+        end.fate = kEscaped;
+        return;
+    }
     uint4 blk = make_uint4(0, 0, 0, 0);
     int have = -1;
     float clock = ph.t0;        // time at the start of the current segment (ns)

@@ -257,6 +257,25 @@ def test_batch_graph_replay_matches_eager_single_source(R):
         assert agree.mean() >= 0.999
 
 
+def test_track_below_threshold_gives_no_light(R, orc):
+    """Device tracks are not checked on the host: photons of a track with n beta <= 1 come out
+    ESCAPED untraced; the photons of the tracks before it are the oracle's, those after it are traced."""
+    cfg = I.config(3)
+    rng = np.random.default_rng(8)
+    tracks = I.sample_tracks(rng, 6)
+    tracks[2, 7] = I.f32(0.99)                      # 1.0014 * 0.99 < 1
+    src = I.batch_source(tracks, np.full(6, 500))
+    gs = R.Scene(cfg["scene"])
+    out = R.propagate_batch(gs, src, 99, tune=R.tuning(64, 64, 1))
+    fate = to_np(out["fate"])
+    assert np.all(fate[1000:1500] == R.ESCAPED)
+    assert (fate[1500:] != R.ESCAPED).mean() > 0.5
+    ref = orc.propagate(cfg["scene"], I.batch_source(tracks[:2], np.full(2, 500)), 1000, 99)
+    sub = {k: to_np(out[k])[:1000] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    compare(sub, ref, min_agree=0.99, label="tracks before the dead one")
+    assert gs.status() == 0
+
+
 def test_batch_graph_follows_every_source_field(R):
     """The captured batch graph is reused only while all launch arguments match: switching the
     pre-filter or the dispersion on the same batch struct and outputs must change the photons."""
