@@ -307,15 +307,62 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
 constexpr int kForwardBlock = 256;
 constexpr int kForwardBlocksPerCu = 8;
 
+constexpr int kSortGroup = 1024;   // photons regrouped together by cone azimuth
+constexpr int kSortBins = 128;
+
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                                 uint64_t first, uint64_t seed) {
     extern __shared__ uint32_t lds_stack[];
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        uint64_t i = base + threadIdx.x;
-        int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
-        if (out.fate_counts) tally_wave(cnt, fate);
+    uint32_t *perm = lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64);
+    uint32_t *bins = perm + kSortGroup;
+    const bool regroup = S.has_mesh && src.kind != 2;
+    if (!regroup) {
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+            uint64_t i = base + threadIdx.x;
+            int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+            if (out.fate_counts) tally_wave(cnt, fate);
+        }
+    } else {
+        // Photons of one group whose cone azimuths are close meet the same
+        // parts of the scene: counting-sort the group by the azimuth's
+        // uniform (word 0 of the photon's first Philox block) so that each
+        // wave traces neighbours.  Every photon keeps its own id and random
+        // numbers; only the lane that traces it changes.
+        constexpr int per = kSortGroup / kForwardBlock;
+        const uint64_t stride = (uint64_t)gridDim.x * kSortGroup;
+        for (uint64_t base = (uint64_t)blockIdx.x * kSortGroup; base < n; base += stride) {
+            if (threadIdx.x < kSortBins) bins[threadIdx.x] = 0;
+            __syncthreads();
+            uint32_t bin[per], rank[per];
+            for (int j = 0; j < per; ++j) {
+                const uint64_t i = base + (uint64_t)(j * kForwardBlock + threadIdx.x);
+                bin[j] = i < n ? photon_block(seed, first + i, 0).x >> 25 : kSortBins - 1;
+                rank[j] = atomicAdd(bins + bin[j], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) {   // exclusive scan of the 128 bin counts by one wave
+                const uint32_t a = bins[2 * threadIdx.x], b = bins[2 * threadIdx.x + 1];
+                uint32_t incl = a + b;
+                for (int d = 1; d < 64; d <<= 1) {
+                    uint32_t v = __shfl_up(incl, d);
+                    if ((int)threadIdx.x >= d) incl += v;
+                }
+                const uint32_t excl = incl - a - b;
+                bins[2 * threadIdx.x] = excl;
+                bins[2 * threadIdx.x + 1] = excl + a;
+            }
+            __syncthreads();
+            for (int j = 0; j < per; ++j) perm[bins[bin[j]] + rank[j]] = (uint32_t)(j * kForwardBlock + threadIdx.x);
+            __syncthreads();
+            for (int j = 0; j < per; ++j) {
+                const uint64_t i = base + perm[j * kForwardBlock + threadIdx.x];
+                int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+                if (out.fate_counts) tally_wave(cnt, fate);
+            }
+            __syncthreads();
+        }
     }
     if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
@@ -323,10 +370,13 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
                           uint64_t seed, int n_cu, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + kForwardBlock - 1) / kForwardBlock;
+    const bool regroup = S.has_mesh && src.kind != 2;
+    const uint64_t per_block = regroup ? kSortGroup : kForwardBlock;
+    uint64_t blocks = (n + per_block - 1) / per_block;
     uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
     if (blocks > cap) blocks = cap;
-    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + kFates * (kForwardBlock / 64) * sizeof(uint32_t);
+    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + kFates * (kForwardBlock / 64) * sizeof(uint32_t) +
+                 (kSortGroup + kSortBins) * sizeof(uint32_t);
     hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
                        seed);
     return hipGetLastError();
