@@ -325,7 +325,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
         const int blocks[] = {64, 128, 256, 512};
         const int chunks[] = {64, 128, 256, 512, 1024};
         for (int blk : blocks) {
-            int max_bpc = (int)std::min<long>(16, (160L * 1024) / ((long)blk * kStackDepth * 4));
+            int max_bpc = (int)std::min<long>(16, (160L * 1024) / (long)batch_lds_bytes(blk));
             for (int bpc = 1; bpc <= max_bpc; bpc *= 2) {
                 for (int ch : chunks) {
                     rich_tuning t{blk, ch, bpc, 0};

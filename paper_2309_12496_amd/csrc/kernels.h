@@ -25,6 +25,7 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
                           uint64_t first, uint64_t seed, int n_cu, hipStream_t st);
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, hipStream_t st);
+size_t batch_lds_bytes(int block);
 
 struct AdjointArgs {
     const float *grad_uv;       // [N][2] or null

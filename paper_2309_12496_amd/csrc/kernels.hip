@@ -387,11 +387,17 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
 // Each wave repeatedly claims `chunk` consecutive photon ids from a global
 // counter and traces them 64 at a time until the ids run out.  Every wave
 // leaves the loop when a claim starts at or beyond n.
-__global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
+constexpr int kWaveGroup = 256;   // photons a batch wave regroups by cone azimuth
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                     uint64_t seed, unsigned long long *counter, int chunk) {
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
+    const int wave = threadIdx.x >> 6;
+    uint32_t *wperm = lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64) +
+                      (size_t)wave * (kWaveGroup + 64);
+    uint32_t *wbins = wperm + kWaveGroup;
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     while (true) {
         unsigned long long base = 0;
@@ -399,18 +405,59 @@ __global__ __launch_bounds__(512) void batch_kernel(DevScene S, DevSource src, D
         uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
         base = ((unsigned long long)hi << 32) | lo;
         if (base >= n) break;
-        for (int k = 0; k < chunk; k += 64) {
-            uint64_t g = base + (uint64_t)k + (uint64_t)lane;
-            int fate = photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
-            if (out.fate_counts) tally_wave(cnt, fate);
+        // With meshes, each kWaveGroup-photon slice of the chunk is regrouped
+        // by cone azimuth (64 bins of the azimuth's uniform) in this wave's
+        // own LDS region, so that each 64-photon pass traces neighbouring
+        // directions.  A wave's LDS operations complete in order; the fences
+        // keep the compiler from moving them across the phases.
+        const bool regroup = S.has_mesh && chunk >= kWaveGroup;
+        const int group = regroup ? kWaveGroup : 64;
+        for (int k = 0; k < chunk; k += group) {
+            if (regroup) {
+                constexpr int per = kWaveGroup / 64;
+                wbins[lane] = 0;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                uint32_t bin[per], rank[per];
+                for (int j = 0; j < per; ++j) {
+                    const uint64_t g = base + (uint64_t)(k + j * 64 + lane);
+                    bin[j] = g < n ? photon_block(seed, g, 0).x >> 26 : 63u;
+                    rank[j] = atomicAdd(wbins + bin[j], 1u);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const uint32_t c = wbins[lane];
+                uint32_t incl = c;
+                for (int d = 1; d < 64; d <<= 1) {
+                    uint32_t v = __shfl_up(incl, d);
+                    if (lane >= d) incl += v;
+                }
+                wbins[lane] = incl - c;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                for (int j = 0; j < per; ++j)
+                    wperm[min(wbins[bin[j]] + rank[j], (uint32_t)kWaveGroup - 1u)] = (uint32_t)(j * 64 + lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+            for (int j = 0; j < group; j += 64) {
+                const uint32_t off = regroup ? wperm[j + lane] : (uint32_t)(j + lane);
+                const uint64_t g = base + (uint64_t)k + off;
+                int fate = photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+                if (out.fate_counts) tally_wave(cnt, fate);
+            }
+            if (regroup) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
     }
     if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
 
+// Dynamic LDS of the batch kernel: per-lane stacks, per-wave fate tallies,
+// per-wave regrouping buffers.
+size_t batch_lds_bytes(int block) {
+    return (size_t)block * kStackDepth * sizeof(uint32_t) + kFates * (block / 64) * sizeof(uint32_t) +
+           (size_t)(block / 64) * (kWaveGroup + 64) * sizeof(uint32_t);
+}
+
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, hipStream_t st) {
-    size_t lds = (size_t)block * kStackDepth * sizeof(uint32_t) + kFates * (block / 64) * sizeof(uint32_t);
+    size_t lds = batch_lds_bytes(block);
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk);
     return hipGetLastError();
 }
