@@ -28,6 +28,10 @@ namespace rich {
 namespace {
 
 constexpr int kAdjBlock = 256;
+constexpr int kAdjQueue = 128;   // per-wave queue of masked photons: < 64 left over + 64 new
+
+// Accumulator row length rounded up to keep the queue that follows 8-byte aligned.
+__host__ __device__ inline int padded_width(int n_par) { return (n_par + 2 + 1) & ~1; }
 constexpr int kMaxRefl = 4;
 constexpr uint32_t kKindCap = 0u, kKindPlane = 1u, kKindFacet = 2u;
 
@@ -132,6 +136,9 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
     float *acc_all = reinterpret_cast<float *>(lds + (size_t)blockDim.x * kStackDepth);
     float *acc = acc_all + wave * width;
     for (int j = lane; j < width; j += 64) acc[j] = 0.0f;
+    // per-wave queue of masked photon indices (see below)
+    uint64_t *queue = reinterpret_cast<uint64_t *>(acc_all + (size_t)waves * padded_width(a.n_par)) +
+                      (size_t)wave * kAdjQueue;
 
     const DetDev &det = *S.det;
     // Squared residual cut; a negative or NaN cut admits no photon.
@@ -140,11 +147,32 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
         float c = *a.residual_cut;
         cut2 = c >= 0.0f ? c * c : -1.0f;
     }
+    // Masks usually keep a few percent of the photons.  Each wave scans its
+    // fixed share of the ids (64 at a time, strided over the grid), queues
+    // the masked ones in order, and traces them 64 at a time, so lanes are
+    // not left idle through a traversal.  The scan order, hence which
+    // photons share a pass and the order of every sum, is fixed.
     const uint64_t nw = (uint64_t)gridDim.x * waves;
-    const uint64_t gw = (uint64_t)blockIdx.x * waves + wave;
-    for (uint64_t base = gw * 64; base < n; base += nw * 64) {
-        uint64_t i = base + (uint64_t)lane;
-        bool act = i < n && (a.mask == nullptr || a.mask[i] != 0);
+    uint64_t base = ((uint64_t)blockIdx.x * waves + wave) * 64;
+    int queued = 0;   // wave-uniform, < 64 between passes
+    while (true) {
+        const bool more = base < n;
+        if (more) {
+            const uint64_t j = base + (uint64_t)lane;
+            const bool want = j < n && (a.mask == nullptr || a.mask[j] != 0);
+            const unsigned long long m = __ballot(want);
+            if (want) queue[queued + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            queued += __popcll(m);
+            base += nw * 64;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (queued < 64) continue;
+        }
+        if (queued == 0) break;
+        const int take = queued < 64 ? queued : 64;
+        queued -= take;
+        bool act = lane < take;
+        const uint64_t i = act ? queue[queued + lane] : 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         PathRecorder rec;
         rec.n_caps = (uint32_t)S.n_caps;
         rec.prim_det = S.prim_det;
@@ -293,7 +321,8 @@ int adjoint_block_size() { return kAdjBlock; }
 hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const AdjointArgs &a, uint64_t n, uint64_t first,
                           uint64_t seed, int n_blocks, hipStream_t st) {
     size_t lds = (size_t)kAdjBlock * kStackDepth * sizeof(uint32_t) +
-                 (size_t)(kAdjBlock / 64) * (a.n_par + 2) * sizeof(float);
+                 (size_t)(kAdjBlock / 64) * padded_width(a.n_par) * sizeof(float) +
+                 (size_t)(kAdjBlock / 64) * kAdjQueue * sizeof(uint64_t);
     hipLaunchKernelGGL(adjoint_kernel, dim3(n_blocks), dim3(kAdjBlock), lds, st, S, src, a, n, first, seed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
