@@ -307,6 +307,25 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
 constexpr int kForwardBlock = 256;
 constexpr int kForwardBlocksPerCu = 8;
 
+// Regrouping bin of photon g among `bins` bins: its cone azimuth's uniform
+// (word 0 of its first Philox block) in bins 0..bins-2, and the last bin
+// for photons the pre-filter rejects (so kept photons fill waves densely).
+__device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSource &src, uint64_t seed, uint64_t g,
+                                                uint64_t i, uint32_t bins) {
+    const uint32_t top = bins - 1u;
+    const uint4 w = photon_block(seed, g, 0);
+    if (src.prefilter && src.n_disp == 0 && src.kind != 2) {
+        // the wavelength alone decides (with dispersion or explicit photons
+        // the rejected ones are not set apart)
+        Photon ph;
+        ph.lambda = rcp(fmaf(-u24(w.y), src.inv_span, src.inv_lmin));
+        if (!prefilter_keep(S, *S.det, src, ph, seed, g)) return top;
+    }
+    if (src.kind == 2) return 0u;
+    const uint32_t b = (uint32_t)(((uint64_t)w.x * bins) >> 32);
+    return b < top ? b : top - 1u;
+}
+
 constexpr int kSortGroup = 1024;   // photons regrouped together by cone azimuth
 constexpr int kSortBins = 128;
 
@@ -316,7 +335,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     uint32_t *perm = lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64);
     uint32_t *bins = perm + kSortGroup;
-    const bool regroup = S.has_mesh && src.kind != 2;
+    const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
     if (!regroup) {
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -338,7 +357,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
             uint32_t bin[per], rank[per];
             for (int j = 0; j < per; ++j) {
                 const uint64_t i = base + (uint64_t)(j * kForwardBlock + threadIdx.x);
-                bin[j] = i < n ? photon_block(seed, first + i, 0).x >> 25 : kSortBins - 1;
+                bin[j] = i < n ? regroup_bin(S, src, seed, first + i, i, kSortBins) : kSortBins - 1;
                 rank[j] = atomicAdd(bins + bin[j], 1u);
             }
             __syncthreads();
@@ -370,7 +389,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
                           uint64_t seed, int n_cu, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const bool regroup = S.has_mesh && src.kind != 2;
+    const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
     const uint64_t per_block = regroup ? kSortGroup : kForwardBlock;
     uint64_t blocks = (n + per_block - 1) / per_block;
     uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
@@ -410,7 +429,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
         // own LDS region, so that each 64-photon pass traces neighbouring
         // directions.  A wave's LDS operations complete in order; the fences
         // keep the compiler from moving them across the phases.
-        const bool regroup = S.has_mesh && chunk >= kWaveGroup;
+        const bool regroup = (S.has_mesh || src.prefilter) && chunk >= kWaveGroup;
         const int group = regroup ? kWaveGroup : 64;
         for (int k = 0; k < chunk; k += group) {
             if (regroup) {
@@ -420,7 +439,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
                 uint32_t bin[per], rank[per];
                 for (int j = 0; j < per; ++j) {
                     const uint64_t g = base + (uint64_t)(k + j * 64 + lane);
-                    bin[j] = g < n ? photon_block(seed, g, 0).x >> 26 : 63u;
+                    bin[j] = g < n ? regroup_bin(S, src, seed, g, g, 64u) : 63u;
                     rank[j] = atomicAdd(wbins + bin[j], 1u);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
