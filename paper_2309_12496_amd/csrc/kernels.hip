@@ -346,9 +346,11 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
     } else {
         // Photons of one group whose cone azimuths are close meet the same
         // parts of the scene: counting-sort the group by the azimuth's
-        // uniform (word 0 of the photon's first Philox block) so that each
-        // wave traces neighbours.  Every photon keeps its own id and random
-        // numbers; only the lane that traces it changes.
+        // uniform (word 0 of the photon's first Philox block), with the
+        // photons the pre-filter rejects in the last bin, so that each wave
+        // traces neighbours and kept photons fill whole waves.  Every photon
+        // keeps its own id and random numbers; only the lane that traces it
+        // changes.
         constexpr int per = kSortGroup / kForwardBlock;
         const uint64_t stride = (uint64_t)gridDim.x * kSortGroup;
         for (uint64_t base = (uint64_t)blockIdx.x * kSortGroup; base < n; base += stride) {
