@@ -26,12 +26,14 @@ namespace {
 
 // Makes the scene's device current for the lifetime of a call.
 struct DeviceGuard {
-    int prev = 0;
-    explicit DeviceGuard(int dev) {
+    int prev = 0, dev = 0;
+    explicit DeviceGuard(int d) : dev(d) {
         (void)hipGetDevice(&prev);
-        (void)hipSetDevice(dev);
+        if (prev != dev) (void)hipSetDevice(dev);
     }
-    ~DeviceGuard() { (void)hipSetDevice(prev); }
+    ~DeviceGuard() {
+        if (prev != dev) (void)hipSetDevice(prev);
+    }
 };
 
 #define RICH_HIP(call)                                                                            \

@@ -266,3 +266,25 @@ def test_alignment_fit_recovers_meshed_tilts(R, orc):
     p = to_np(p).astype(np.float64)
     assert gs.status() == 0
     assert np.abs(p[lit, :2] - tp[lit, :2]).max() < 0.5e-6
+
+
+def test_graph_captured_fit_matches_eager(R, orc):
+    """The fit's step captured once in a graph and replayed gives exactly the eager trajectory, every step:
+    two graph fits with eager work and synchronisations between them against one eager fit."""
+    import torch
+    from paper_2309_12496_amd.align import fit_alignment
+    scene = I.scene_g4()
+    src, seed, tp, tgt, on, lit = _fit_problem(orc, 4, scene, 300, 100, 50)
+    gs = R.Scene(scene)
+    p_e, l_e = fit_alignment(gs, src, seed, tgt["hit_uv"], on, steps=120, lr=0.3, graph=False)
+    runs = []
+    for rep in range(2):
+        p_g, l_g = fit_alignment(gs, src, seed, tgt["hit_uv"], on, steps=120, lr=0.3, graph=True)
+        runs.append((to_np(p_g).copy(), to_np(l_g).copy()))
+        x = torch.ones(1 << 20, device="cuda").cumsum(0)   # eager work between the graph fits
+        torch.cuda.synchronize()
+        assert float(x[-1]) == float(1 << 20)
+    for p_g, l_g in runs:
+        assert np.array_equal(l_g, to_np(l_e)), np.flatnonzero(l_g != to_np(l_e))[:5]
+        assert np.array_equal(p_g, to_np(p_e))
+    assert gs.status() == 0

@@ -77,6 +77,20 @@ def test_extreme_ids_and_seeds(R, orc, c1, first, seed):
     compare(out, ref, min_agree=0.99, label=f"C1 first={first} seed={seed}")
 
 
+@pytest.mark.parametrize("n,first,prefilter", [(1, 0, False), (63, 7, False), (1025, 1000, False), (3000, 123457, False),
+                                                (1025, 5, True), (2500, 999, True)])
+def test_meshed_regrouping_at_ragged_sizes(R, orc, c2, n, first, prefilter):
+    """The regrouping pass (groups of 1024 sorted by azimuth, pre-filter rejects last) at sizes and
+    offsets that leave partial groups, photon by photon against the oracle."""
+    cfg, gs, os_ = c2
+    src = I.with_prefilter(cfg["source"]) if prefilter else cfg["source"]
+    out = R.propagate(gs, src, n, cfg["seed"], first_id=first)
+    ref = orc.propagate(os_, src, n, cfg["seed"], first_id=first)
+    compare(out, ref, min_agree=0.99, label=f"C2 regroup n={n} first={first} pf={prefilter}")
+    counts = to_np(out["fate_counts"])
+    assert counts.sum() == n and counts[R.PREFILTERED] == int((ref["fate"] == orc.PREFILTERED).sum())
+
+
 def test_zero_photons_is_a_no_op(R, c1):
     import torch
     cfg, gs, _ = c1
