@@ -302,7 +302,7 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
     }
 }
 
-// ---------------------------------------------------------------- forward: grid-stride over photons
+// ---------------------------------------------------------------- forward: regrouped groups or grid-stride
 
 constexpr int kForwardBlock = 256;
 constexpr int kForwardBlocksPerCu = 8;
@@ -410,8 +410,10 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
 // leaves the loop when a claim starts at or beyond n.
 constexpr int kWaveGroup = 256;   // photons a batch wave regroups by cone azimuth
 
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
-                                                    uint64_t seed, unsigned long long *counter, int chunk) {
+// Held to 128 VGPRs (4 waves per SIMD; 12 bytes of spills per lane): left
+// alone the compiler takes a few more registers and a wave less.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(
+    DevScene S, DevSource src, DevOutputs out, uint64_t n, uint64_t seed, unsigned long long *counter, int chunk) {
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
@@ -426,12 +428,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
         uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
         base = ((unsigned long long)hi << 32) | lo;
         if (base >= n) break;
-        // With meshes, each kWaveGroup-photon slice of the chunk is regrouped
-        // by cone azimuth (64 bins of the azimuth's uniform) in this wave's
-        // own LDS region, so that each 64-photon pass traces neighbouring
-        // directions.  A wave's LDS operations complete in order; the fences
-        // keep the compiler from moving them across the phases.
-        const bool regroup = (S.has_mesh || src.prefilter) && chunk >= kWaveGroup;
+        // With meshes (or the pre-filter), each kWaveGroup-photon slice of the
+        // chunk is regrouped by cone azimuth (64 bins of the azimuth's
+        // uniform; pre-filter rejects last) in this wave's own LDS region, so
+        // that each 64-photon pass traces neighbouring directions.  Only
+        // chunks made of whole slices are regrouped: a partial slice would
+        // reach into the next claim.  A wave's LDS operations complete in
+        // order; the fences keep the compiler from moving them across phases.
+        const bool regroup = (S.has_mesh || src.prefilter) && chunk % kWaveGroup == 0;
         const int group = regroup ? kWaveGroup : 64;
         for (int k = 0; k < chunk; k += group) {
             if (regroup) {

@@ -290,6 +290,22 @@ def test_track_below_threshold_gives_no_light(R, orc):
     assert gs.status() == 0
 
 
+@pytest.mark.parametrize("chunk", [64, 320, 768])
+def test_batch_chunks_that_are_not_whole_regroup_slices(R, orc, chunk):
+    """Chunks need only be multiples of 64; those that are not whole 256-photon regrouping slices
+    must still trace every photon exactly once."""
+    cfg = I.config(3)
+    gs = R.Scene(cfg["scene"])
+    out = R.propagate_batch(gs, cfg["source"], cfg["seed"], tune=R.tuning(128, chunk, 2))
+    n = cfg["n_photons"]
+    assert int(to_np(out["fate_counts"]).sum()) == n
+    _hist_counts_consistent(out, gs.nx, gs.ny)
+    ids = np.arange(5, n, 997, dtype=np.uint64)
+    ref = orc.propagate(cfg["scene"], cfg["source"], 0, cfg["seed"], ids=ids)
+    sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    compare(sub, ref, label=f"C3 chunk {chunk}")
+
+
 def test_batch_graph_follows_every_source_field(R):
     """The captured batch graph is reused only while all launch arguments match: switching the
     pre-filter or the dispersion on the same batch struct and outputs must change the photons."""
