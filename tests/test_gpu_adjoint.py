@@ -196,6 +196,25 @@ def _cut_in_gap(r, lo_q=0.3, hi_q=0.7, clearance=5e-3):
     return 0.5 * (s[j] + s[j + 1])
 
 
+def test_dispersive_source_gradient_matches_oracle(R, orc):
+    """The adjoint retraces photons whose wavelength and cone come from the dispersive generator."""
+    scene = I.scene_g4()
+    rng = np.random.default_rng(1004)
+    src = I.with_dispersion(I.batch_source(I.sample_tracks(rng, 100), np.full(100, 1000)))
+    n, seed = 100_000, I.SEED_BASE + 4
+    tp = I.perturbed_params(4, scene)
+    target = orc.propagate(orc.Scene(scene, params=tp), src, n, seed)
+    cur = orc.propagate(orc.Scene(scene), src, n, seed, jacobian=True)
+    on = lambda r: np.isin(r["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    mask = on(target) & on(cur) & (target["edge_margin"] > 0.05) & (cur["edge_margin"] > 0.05)
+    loss_ref, grad_ref, nuse = orc.mse_loss_and_grad(cur, target["hit_uv"], mask, scene["params"].shape[0])
+    assert nuse > 1000
+    gs = R.Scene(scene)
+    grad, loss = R.adjoint(gs, src, seed, targets=target["hit_uv"], mask=mask)
+    assert abs(float(loss) / loss_ref - 1) < 1e-4
+    grad_close(to_np(grad), grad_ref, label="dispersive")
+
+
 def test_residual_cut_matches_oracle(R, orc, c4small):
     """Fused loss with dev_residual_cut: photons beyond the cut are left out of loss, count and gradient."""
     import torch
