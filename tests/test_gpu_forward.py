@@ -362,3 +362,29 @@ def test_prefilter_batch_and_validation(R, orc):
     with pytest.raises(R.RichError) as e:
         R.rich_propagate(gs.handle, s, 10, 1, 0, o)
     assert e.value.code == R.RICH_EINVAL
+
+
+def test_autotune_cache_file(R, orc, tmp_path, monkeypatch):
+    """rich_propagate_batch with no tuning autotunes once and stores the shape under RICH_TUNE_CACHE;
+    another scene of the same kind reads it back instead of tuning; an invalid stored shape is replaced."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("RICH_TUNE_CACHE", str(path))
+    cfg = I.config(3)
+    src = I.poisson_batch(3, 512, 1000.0, clip=(50, 5000))
+    gs = R.Scene(cfg["scene"])
+    first = R.propagate_batch(gs, src, cfg["seed"])
+    stored = json.loads(path.read_text())
+    assert len(stored) == 1
+    key, (block, chunk, bpc) = next(iter(stored.items()))
+    assert block in (64, 128, 256, 512) and chunk % 64 == 0 and bpc >= 1
+    path.write_text(json.dumps({key: [64, 128, 1]}))
+    text = path.read_text()
+    again = R.propagate_batch(R.Scene(cfg["scene"]), src, cfg["seed"])
+    assert path.read_text() == text                      # read, not re-tuned
+    for k in ("fate", "pixel", "hit_xyz"):
+        assert np.array_equal(to_np(first[k]), to_np(again[k]), equal_nan=True), k
+    path.write_text(json.dumps({key: [63, 100, 0]}))      # not a valid shape: tuned and stored again
+    R.propagate_batch(R.Scene(cfg["scene"]), src, cfg["seed"])
+    block, chunk, bpc = json.loads(path.read_text())[key]
+    assert block in (64, 128, 256, 512) and chunk % 64 == 0 and bpc >= 1
