@@ -304,7 +304,9 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
 /* Propagate every photon of a batch (n_photons = offsets[n_tracks]) in one
  * persistent launch replayed from a captured HIP graph.  tune = NULL picks the
  * launch shape with the autotuner (cached per scene and in the JSON file named
- * by RICH_TUNE_CACHE, if set). */
+ * by RICH_TUNE_CACHE, if set; tuning synchronises the stream).  The call
+ * captures and launches its own graph, so it is not itself meant to be
+ * captured into a caller's graph. */
 rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
                                  const rich_outputs *out, const rich_tuning *tune, hipStream_t stream);
 
@@ -327,7 +329,9 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
  *     fits; a negative or NaN cut leaves every photon out).  Giving it in dev_grad_uv
  *     mode is RICH_EINVAL.
  * dev_grad_params [n_segments][6] is overwritten.  The sums are deterministic
- * (fixed reduction order). */
+ * (fixed reduction order).  The first call, and a call with more photons than
+ * any before, allocates the scene's partial-sum buffer: a caller that
+ * captures this call in a graph makes one such call first. */
 rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
                                    uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,

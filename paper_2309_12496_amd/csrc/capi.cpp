@@ -295,7 +295,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     // scratch outputs so the caller's accumulating outputs stay untouched
     uint8_t *fate = nullptr;
     int32_t *pixel = nullptr;
-    float *xyz = nullptr, *uv = nullptr;
+    float *xyz = nullptr, *uv = nullptr, *time = nullptr;
     uint32_t *hist = nullptr;
     unsigned long long *counts = nullptr, *counter = nullptr;
     size_t nh = (size_t)s->nx * s->ny;
@@ -304,6 +304,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     e = e == hipSuccess ? hipMalloc(&pixel, 4 * n_t) : e;
     e = e == hipSuccess ? hipMalloc(&xyz, 12 * n_t) : e;
     e = e == hipSuccess ? hipMalloc(&uv, 8 * n_t) : e;
+    e = e == hipSuccess ? hipMalloc(&time, 4 * n_t) : e;
     e = e == hipSuccess ? hipMalloc(&hist, 4 * nh) : e;
     e = e == hipSuccess ? hipMalloc(&counts, 8 * RICH_N_FATES) : e;
     e = e == hipSuccess ? hipMalloc(&counter, 8) : e;
@@ -320,6 +321,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
         out.pixel = pixel;
         out.hit_xyz = xyz;
         out.hit_uv = uv;
+        out.hit_time = time;
         out.histogram = hist;
         out.fate_counts = counts;
         float best = INFINITY;
@@ -357,7 +359,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    void *ptrs[] = {fate, pixel, xyz, uv, hist, counts, counter};
+    void *ptrs[] = {fate, pixel, xyz, uv, time, hist, counts, counter};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     return st;
