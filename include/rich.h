@@ -319,7 +319,8 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
  * the segment parameters, at the scene's current parameters, for the photons
  * of either `src` (ids first_photon_id..) or `batch` (ids 0..), exactly one
  * non-NULL.  Interior derivative: visibility changes at edges are ignored.
- * Only photons with dev_mask[i] != 0 whose path ends on the pixel grid count.
+ * Only photons with dev_mask[i] != 0 (dev_mask NULL: every photon) whose path
+ * ends on the pixel grid count.
  *   dev_grad_uv != NULL: dev_grad_params = sum_i J_i^T dev_grad_uv[i];
  *   dev_targets != NULL (fused loss): L = (1/N) sum_i |uv_i - target_i|^2 over
  *     the N counted photons, dev_grad_params = dL/dp, *dev_loss = L.
@@ -328,7 +329,8 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
  *     |uv_i - target_i| exceeds it are not counted (outlier rejection for
  *     fits; a negative or NaN cut leaves every photon out).  Giving it in dev_grad_uv
  *     mode is RICH_EINVAL.
- * dev_grad_params [n_segments][6] is overwritten.  The sums are deterministic
+ * dev_grad_params [n_segments][6] is overwritten (zeros, and a zero loss, when
+ * no photon counts, n_photons = 0 included).  The sums are deterministic
  * (fixed reduction order).  The first call, and a call with more photons than
  * any before, allocates the scene's partial-sum buffer: a caller that
  * captures this call in a graph makes one such call first. */

@@ -307,3 +307,28 @@ def test_graph_captured_fit_matches_eager(R, orc):
         assert np.array_equal(l_g, to_np(l_e)), np.flatnonzero(l_g != to_np(l_e))[:5]
         assert np.array_equal(p_g, to_np(p_e))
     assert gs.status() == 0
+
+
+def test_adjoint_with_nothing_to_differentiate(R):
+    """An all-zero mask, or no photons at all, overwrites the gradient and the loss with zeros
+    (no division by a zero photon count)."""
+    import torch
+    scene = I.scene_g4()
+    src = I.batch_source(I.sample_tracks(np.random.default_rng(1004), 8), np.full(8, 500))
+    gs = R.Scene(scene)
+    b, keep, n = R.make_batch(src)
+    g = torch.full((gs.n_segments, 6), 5.0, device="cuda")
+    loss = torch.full((1,), 5.0, device="cuda")
+    tg = torch.zeros((n, 2), device="cuda")
+    for mask, count in ((torch.zeros(n, dtype=torch.uint8, device="cuda"), n), (None, 0)):
+        R.rich_propagate_adjoint(gs.handle, None, b, count, I.SEED_BASE + 4, 0, None, tg, mask, None, g, loss)
+        torch.cuda.synchronize()
+        assert not to_np(g).any() and float(loss) == 0.0
+        g.fill_(5.0)
+        loss.fill_(5.0)
+    # upstream-gradient mode with a zero upstream gradient
+    gin = torch.zeros((n, 2), device="cuda")
+    R.rich_propagate_adjoint(gs.handle, None, b, n, I.SEED_BASE + 4, 0, gin, None, None, None, g, None)
+    torch.cuda.synchronize()
+    assert not to_np(g).any()
+    assert gs.status() == 0

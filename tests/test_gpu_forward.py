@@ -388,3 +388,39 @@ def test_autotune_cache_file(R, orc, tmp_path, monkeypatch):
     R.propagate_batch(R.Scene(cfg["scene"]), src, cfg["seed"])
     block, chunk, bpc = json.loads(path.read_text())[key]
     assert block in (64, 128, 256, 512) and chunk % 64 == 0 and bpc >= 1
+
+
+def test_batch_with_empty_tracks(R, orc):
+    """Tracks with no photons (first, in runs in the middle, last) take no ids: every photon
+    still belongs to the track its offset range names, on the meshed scene with regrouping."""
+    cfg = I.config(3)
+    rng = np.random.default_rng(31)
+    tracks = I.sample_tracks(rng, 40)
+    counts = rng.integers(1, 700, size=40)
+    counts[[0, 7, 8, 9, 21, 39]] = 0
+    src = I.batch_source(tracks, counts)
+    n = int(counts.sum())
+    gs = R.Scene(cfg["scene"])
+    for tune in (R.tuning(256, 256, 4), R.tuning(64, 64, 2)):
+        out = R.propagate_batch(gs, src, cfg["seed"], tune=tune)
+        assert int(to_np(out["fate_counts"]).sum()) == n
+        ids = np.arange(0, n, 7, dtype=np.uint64)
+        ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
+        sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+        compare(sub, ref, label=f"empty tracks {tune.block}x{tune.chunk}")
+    assert gs.status() == 0
+
+
+def test_batch_without_photons_is_a_no_op(R):
+    """Every track empty: n_photons = 0 returns at once and writes nothing."""
+    import torch
+    cfg = I.config(3)
+    src = I.batch_source(I.sample_tracks(np.random.default_rng(5), 3), [0, 0, 0])
+    gs = R.Scene(cfg["scene"])
+    b, keep, n = R.make_batch(src)
+    assert n == 0
+    t, o = R.alloc_outputs(gs, 1)
+    t["fate"].fill_(77)
+    R.rich_propagate_batch(gs.handle, b, 0, cfg["seed"], o, None)
+    torch.cuda.synchronize()
+    assert int(t["fate"][0]) == 77 and int(t["histogram"].sum()) == 0 and int(t["fate_counts"].sum()) == 0
