@@ -31,7 +31,9 @@
  *   - Launches on one scene share small device counters (the batch work
  *     counter, the fate-count slots, the adjoint partial sums), so work on
  *     one scene must not run concurrently on two streams.  Calls on one
- *     scene from one stream are ordered.
+ *     scene from one stream are ordered.  A scene's host state (captured
+ *     batch graph, tuning cache) is not locked: one host thread at a time
+ *     per scene; different scenes are independent.
  */
 #ifndef RICH_H
 #define RICH_H
