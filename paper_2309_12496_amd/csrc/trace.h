@@ -340,8 +340,13 @@ __device__ __forceinline__ bool hit_box(const float *lo, const float *hi, const 
 }
 
 // Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013), two-sided.
+// Each edge function is two rounded products and one difference, never
+// contracted into an FMA: only then does a triangle's edge function equal the
+// exact negative of its neighbour's for their shared edge, so a ray through
+// that edge cannot be rejected by both.
 __device__ __forceinline__ bool hit_tri(const Ray &r, const Shear &sh, const float4 &a, const float4 &b,
                                         const float4 &c, float tmin, float &t_out) {
+#pragma clang fp contract(off)
     V3 A = V3{a.x, a.y, a.z} - r.o, B = V3{b.x, b.y, b.z} - r.o, C = V3{c.x, c.y, c.z} - r.o;
     float Akz = comp(A, sh.kz), Bkz = comp(B, sh.kz), Ckz = comp(C, sh.kz);
     float Ax = fmaf(-sh.sx, Akz, comp(A, sh.kx)), Ay = fmaf(-sh.sy, Akz, comp(A, sh.ky));
@@ -358,7 +363,7 @@ __device__ __forceinline__ bool hit_tri(const Ray &r, const Shear &sh, const flo
     if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
     float det = U + V + W;
     if (det == 0.0f) return false;
-    float T = U * (sh.sz * Akz) + V * (sh.sz * Bkz) + W * (sh.sz * Ckz);
+    float T = fmaf(U, sh.sz * Akz, fmaf(V, sh.sz * Bkz, W * (sh.sz * Ckz)));
     float t = T * rcp(det);
     if (!(t > tmin)) return false;
     t_out = t;

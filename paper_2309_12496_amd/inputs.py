@@ -434,6 +434,63 @@ def scene_t1(radius=2000.0, detector_z=100.0, n_pix=200, pitch=3.0):
     }
 
 
+def scene_coincident(mirror_first, half=200.0, plane_z=500.0, detector_z=100.0, n_pix=200, pitch=3.0):
+    """Tie and watertightness scene: two copies of one flat square at z = plane_z, a fan of eight
+    triangles around its centre facing -z, one copy a mirror and one an absorber, listed mirror
+    first or absorber first; the mirror copy also carries zero-area triangles (three collinear
+    vertices along a fan edge, a repeated vertex).  A detector at z = detector_z faces +z;
+    reflectivity and QE are 1.  Every photon leaving from between them toward the square meets
+    both copies at exactly the same distance, so the first-listed copy (lower primitive index)
+    decides its fate."""
+    c = np.array([0.0, 0.0, plane_z])
+    ring = [(half, 0.0), (half, half), (0.0, half), (-half, half), (-half, 0.0), (-half, -half),
+            (0.0, -half), (half, -half)]
+    ring = [np.array([x, y, plane_z]) for x, y in ring]
+    fan = np.array([[c, ring[(k + 1) % 8], ring[k]] for k in range(8)])   # normals along -z
+    degenerate = np.array([[c, c + [0.5 * half, 0.0, 0.0], c + [half, 0.0, 0.0]],
+                           [ring[2], ring[2], c]])
+    mirror = {"vertices": np.concatenate([fan, degenerate]), "material": MIRROR, "segment": -1}
+    absorber = {"vertices": fan.copy(), "material": ABSORBER, "segment": -1}
+    h = 0.5 * n_pix * pitch
+    det = {"center": np.array([0.0, 0.0, detector_z]), "normal": np.array([0.0, 0.0, 1.0]),
+           "axis_u": np.array([1.0, 0.0, 0.0]), "axis_v": np.array([0.0, -1.0, 0.0]),
+           "half": np.array([h, h]), "pitch": pitch, "nx": n_pix, "ny": n_pix,
+           "qe_lambda": np.array([200.0, 600.0]), "qe_value": np.array([1.0, 1.0])}
+    return {
+        "name": "coincident-" + ("mirror" if mirror_first else "absorber") + "-first",
+        "materials": _materials(unit_reflectivity=True),
+        "segments": {"pivot": np.zeros((0, 3)), "u0": np.zeros((0, 3)), "e1": np.zeros((0, 3)),
+                     "e2": np.zeros((0, 3)), "radius0": np.zeros(0)},
+        "params": np.zeros((0, 6)),
+        "caps": _empty_caps(),
+        "rects": _empty_rects(),
+        "meshes": [mirror, absorber] if mirror_first else [absorber, mirror],
+        "detector": det,
+        "box": {"lo": np.array([-3000.0, -3000.0, -3000.0]), "hi": np.array([3000.0, 3000.0, 3000.0])},
+        "max_bounces": 16,
+        "t_min": 1e-2,
+    }
+
+
+def coincident_photons(seed=77, start_z=200.0):
+    """Explicit photons for scene_coincident: straight up through the fan's centre, through points
+    on its inner edges and on its outer boundary, through random interior points, and slightly
+    tilted from random interior points."""
+    rng = np.random.default_rng(seed)
+    exact = [(0, 0), (100, 0), (0, 100), (-100, 0), (0, -100), (100, 100), (-50, -50), (150, -150),
+             (-70, 70), (200, 50), (-200, -120), (30, 200), (-10, -200), (200, 200)]
+    xy = np.concatenate([np.array(exact, np.float64), rng.uniform(-190.0, 190.0, size=(200, 2)),
+                         rng.uniform(-120.0, 120.0, size=(300, 2))])
+    n = len(xy)
+    o = np.column_stack([xy, np.full(n, start_z)])
+    d = np.zeros((n, 3))
+    d[:, 2] = 1.0
+    tilt = rng.uniform(-0.1, 0.1, size=(300, 2))
+    d[-300:, :2] = tilt
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return explicit_source(o, d, np.full(n, 400.0))
+
+
 def film_paper(width=1320, height=620, sigma=0.5, threshold=45.0):
     """The paper's camera and film (Section 4.4): 1320 x 620 pixels, camera 478.69 mm in front of the
     detector, 116.38 degree field of view, hit threshold 45 of 255.  The reconstruction filter is not

@@ -424,3 +424,41 @@ def test_batch_without_photons_is_a_no_op(R):
     R.rich_propagate_batch(gs.handle, b, 0, cfg["seed"], o, None)
     torch.cuda.synchronize()
     assert int(t["fate"][0]) == 77 and int(t["histogram"].sum()) == 0 and int(t["fate_counts"].sum()) == 0
+
+
+def test_coincident_triangles_and_closed_edges(R, orc):
+    """Two coincident copies of a fan-triangulated square, a mirror and an absorber: the copy listed
+    first (lower primitive index) decides every photon, also photons through the fan's centre, along
+    its inner edges and on its outer boundary (edges are closed and shared edges leak nothing);
+    zero-area triangles in the mesh are never hit."""
+    src = I.coincident_photons()
+    n = len(src["lambda"])
+    for mirror_first, fate in ((True, R.DETECTED), (False, R.ABSORBED)):
+        sc = I.scene_coincident(mirror_first)
+        gs = R.Scene(sc)
+        out = R.propagate(gs, src, n, 1)
+        assert (to_np(out["fate"]) == fate).all(), sc["name"]
+        compare(out, orc.propagate(sc, src, n, 1), label=sc["name"])
+
+
+def test_closed_triangle_box_is_watertight(R, orc):
+    """Photons from inside a closed tessellated box (10,092 triangles), aimed at its vertices and
+    edge midpoints, never slip out between triangles."""
+    import copy
+    box = I.box_mesh(I.BOX_LO, I.BOX_HI, 29)
+    sc = copy.deepcopy(I.scene_g2())
+    sc["box"] = None
+    sc["meshes"] = [{"vertices": box, "material": I.ABSORBER, "segment": -1}]
+    rng = np.random.default_rng(9)
+    m = 20000
+    o = rng.uniform(I.BOX_LO + 10, I.BOX_HI - 10, size=(m, 3))
+    verts = box.reshape(-1, 3)
+    k = rng.integers(0, len(box), m // 2)
+    tgt = np.concatenate([verts[rng.integers(0, len(verts), m // 2)], 0.5 * (box[k, 0] + box[k, 1])])
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    src = I.explicit_source(o, d, np.full(m, 400.0))
+    gs = R.Scene(sc)
+    out = R.propagate(gs, src, m, 3)
+    assert not (to_np(out["fate"]) == R.ESCAPED).any()
+    compare(out, orc.propagate(sc, src, m, 3), label="closed box")

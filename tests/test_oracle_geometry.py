@@ -342,3 +342,18 @@ def test_prefilter_rejects_non_mirror_material(orc):
     src = I.with_prefilter(I.point_source(), mirror_materials=(I.ABSORBER,))
     with pytest.raises(ValueError):
         orc.propagate(I.scene_g1(), src, 10, seed=1)
+
+
+def test_coincident_copies_decide_by_listing_order(orc):
+    """Whole-path version of the tie rule on two coincident fan-triangulated squares (mirror and
+    absorber): the first-listed copy decides every photon, photons along shared and outer edges
+    included; photons sent straight up come straight back down under their start point."""
+    src = I.coincident_photons()
+    n = len(src["lambda"])
+    up = src["d"][:, 2] == 1.0
+    for mirror_first, fate in ((True, orc.DETECTED), (False, orc.ABSORBED)):
+        r = orc.propagate(I.scene_coincident(mirror_first), src, n, 1)
+        assert np.all(r["fate"] == fate)
+        if mirror_first:
+            # detector axes: u along +x, v along -y
+            assert np.array_equal(r["hit_uv"][up], np.column_stack([src["o"][up, 0], -src["o"][up, 1]]))
