@@ -342,6 +342,46 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
                                    const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
                                    hipStream_t stream);
 
+/* Optimiser of the alignment fit (extension beyond the paper, built on
+ * rich_propagate_adjoint): one Adam step (Kingma and Ba, ICLR 2015) over the
+ * segment parameters in normalised coordinates z = (p - p0) / scale, with
+ * the step size decaying from lr (step 1) towards lr_final along a cosine:
+ *   size_t = lr_final + (lr - lr_final) (1 + cos(pi (t - 1) / n_steps)) / 2,
+ *   g = dL/dp * scale (0 in columns not free),
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   z -= size_t (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ *   p = p0 + z * scale,
+ * written into the scene (cap centres, instance transforms and top-level
+ * boxes refreshed on the stream, as by rich_set_mirror_params). */
+typedef struct rich_fit {
+    int32_t n_steps;          /* length of the step-size schedule, >= 1 */
+    int32_t reserved;
+    double lr, lr_final;      /* step sizes in normalised units, >= 0 */
+    double beta1, beta2;      /* moment decay rates in [0, 1) */
+    double eps;               /* > 0 */
+    double scale[6];          /* > 0: column units of z (tx, ty [rad], R, dx, dy, dz [mm]) */
+    int32_t free[6];          /* nonzero: the column is fitted */
+    double outlier_cut;       /* residual cut after the step: outlier_cut sqrt(loss) + cut_floor (mm) */
+    double cut_floor;
+} rich_fit;
+
+/* One fit step on `stream`, after the step's rich_propagate_adjoint (fused
+ * loss mode) has written dev_grad [n_segments][6] and dev_loss [1]:
+ *   dev_p0 [n_segments][6]   parameters at z = 0 (read);
+ *   dev_state [3 * 6 * n_segments + 1]   z, m, v, then the number of steps
+ *            taken (FP32), zeroed by the caller before the first step and
+ *            updated in place;
+ *   dev_params [n_segments][6] or NULL   receives the new parameters;
+ *   dev_losses [n_steps] or NULL   dev_losses[t - 1] = *dev_loss at step t;
+ *   dev_cut [1] or NULL   becomes outlier_cut sqrt(loss) + cut_floor, or
+ *            +inf when the loss is 0 (no photon counted), for the next
+ *            adjoint's dev_residual_cut.
+ * Nothing is allocated and nothing waits for the host, so the adjoint and
+ * this call can be captured together in a graph and replayed. */
+rich_status rich_fit_step(rich_scene *s, const rich_fit *fit, const float *dev_p0, const float *dev_grad,
+                          const float *dev_loss, float *dev_state, float *dev_params, float *dev_losses,
+                          float *dev_cut, hipStream_t stream);
+
 /* Film read-out emulation (Section 4.4): the paper detects photons by
  * imaging the detector plane with a pinhole camera onto a film and counting
  * pixels above an intensity threshold (which spreads one photon over several

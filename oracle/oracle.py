@@ -412,3 +412,61 @@ def mse_loss_and_grad(res, targets, mask, n_seg, residual_cut=None):
     contrib = np.einsum("nk,nkp->np", r[has], res["jac"][use][has]) * (2.0 / nuse)
     np.add.at(grad, seg[has], contrib)
     return loss, grad, nuse
+
+
+class AdamFit:
+    """The alignment fit's optimiser in FP64 (Adam, Kingma and Ba, ICLR 2015).
+
+    Parameters move in normalised coordinates z = (p - p0) / scale; at step
+    t = 1, 2, ... with gradient G_t = dL/dp and loss L_t:
+        g = G_t * scale in free columns, 0 elsewhere
+        m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2
+        z = z - size_t * (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+        size_t = lr_final + (lr - lr_final) (1 + cos(pi (t - 1) / n_steps)) / 2
+        p = p0 + z * scale
+    and the residual cut for the next step is outlier_cut sqrt(L_t) + cut_floor
+    (+inf when L_t = 0, and always +inf without outlier_cut).
+    """
+
+    def __init__(self, p0, n_steps, lr, lr_final, scale, free, betas=(0.9, 0.999), eps=1e-12, outlier_cut=None,
+                 cut_floor=0.0):
+        self.p0 = np.asarray(p0, np.float64)
+        self.sc = np.asarray(scale, np.float64)[None, :]
+        self.fm = np.asarray(free, bool)[None, :]
+        self.z = np.zeros_like(self.p0)
+        self.m = np.zeros_like(self.p0)
+        self.v = np.zeros_like(self.p0)
+        self.t = 0
+        self.cut = np.inf
+        self.n_steps, self.lr, self.lr_final, self.betas, self.eps = n_steps, lr, lr_final, betas, eps
+        self.outlier_cut, self.cut_floor = outlier_cut, cut_floor
+
+    @property
+    def p(self):
+        return self.p0 + self.z * self.sc
+
+    def step(self, G, L):
+        b1, b2 = self.betas
+        self.t += 1
+        t = self.t
+        g = np.where(self.fm, np.asarray(G, np.float64) * self.sc, 0.0)
+        self.m = b1 * self.m + (1 - b1) * g
+        self.v = b2 * self.v + (1 - b2) * g * g
+        size = self.lr_final + 0.5 * (self.lr - self.lr_final) * (1 + np.cos(np.pi * (t - 1) / self.n_steps))
+        self.z = self.z - size * (self.m / (1 - b1 ** t)) / (np.sqrt(self.v / (1 - b2 ** t)) + self.eps)
+        if self.outlier_cut is not None:
+            self.cut = self.outlier_cut * np.sqrt(L) + self.cut_floor if L > 0 else np.inf
+        return self.p
+
+
+def adam_fit_steps(p0, grads, losses, n_steps, lr, lr_final, scale, free, betas=(0.9, 0.999), eps=1e-12,
+                   outlier_cut=None, cut_floor=0.0):
+    """AdamFit over given per-step gradients and losses; per-step arrays of
+    params, z, m, v [T, n_seg, 6] and cut [T]."""
+    a = AdamFit(p0, n_steps, lr, lr_final, scale, free, betas, eps, outlier_cut, cut_floor)
+    out = {k: [] for k in ("params", "z", "m", "v", "cut")}
+    for G, L in zip(grads, losses):
+        a.step(G, L)
+        for k in ("p", "z", "m", "v", "cut"):
+            out["params" if k == "p" else k].append(getattr(a, k))
+    return {k: np.array(x) for k, x in out.items()}

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librich.so")
 
-SOURCES = ["kernels.hip", "adjoint.hip", "film.hip", "bvh_build.cpp", "scene.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "film.hip", "fit.hip", "bvh_build.cpp", "scene.cpp", "capi.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions anywhere in the device code

@@ -411,6 +411,53 @@ rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipSt
     return RICH_OK;
 }
 
+rich_status rich_fit_step(rich_scene *s, const rich_fit *fit, const float *dev_p0, const float *dev_grad,
+                          const float *dev_loss, float *dev_state, float *dev_params, float *dev_losses,
+                          float *dev_cut, hipStream_t stream) {
+    if (!s || !fit) return set_error(RICH_EINVAL, "scene and fit must not be NULL");
+    if (s->n_segments == 0) return set_error(RICH_ESTATE, "scene has no parametrised segments");
+    if (!dev_p0 || !dev_grad || !dev_loss || !dev_state)
+        return set_error(RICH_EINVAL, "dev_p0, dev_grad, dev_loss and dev_state are needed");
+    if (fit->n_steps < 1) return set_error(RICH_EINVAL, "fit: n_steps >= 1");
+    if (!(fit->lr >= 0) || !(fit->lr_final >= 0) || !std::isfinite(fit->lr) || !std::isfinite(fit->lr_final))
+        return set_error(RICH_EINVAL, "fit: finite step sizes >= 0");
+    if (!(fit->beta1 >= 0 && fit->beta1 < 1) || !(fit->beta2 >= 0 && fit->beta2 < 1))
+        return set_error(RICH_EINVAL, "fit: beta1 and beta2 in [0, 1)");
+    if (!(fit->eps > 0) || !std::isfinite(fit->eps)) return set_error(RICH_EINVAL, "fit: eps > 0");
+    for (int c = 0; c < 6; ++c)
+        if (!(fit->scale[c] > 0) || !std::isfinite(fit->scale[c])) return set_error(RICH_EINVAL, "fit: scale > 0");
+    if (dev_cut && (!std::isfinite(fit->outlier_cut) || !std::isfinite(fit->cut_floor)))
+        return set_error(RICH_EINVAL, "fit: finite outlier_cut and cut_floor");
+    DeviceGuard g(s->device);
+    FitArgs a;
+    a.n_par = 6 * s->n_segments;
+    a.n_steps = fit->n_steps;
+    a.lr = fit->lr;
+    a.lr_final = fit->lr_final;
+    a.beta1 = fit->beta1;
+    a.beta2 = fit->beta2;
+    a.eps = fit->eps;
+    for (int c = 0; c < 6; ++c) {
+        a.scale[c] = (float)fit->scale[c];
+        a.free[c] = fit->free[c] ? 1 : 0;
+    }
+    a.outlier_cut = (float)fit->outlier_cut;
+    a.cut_floor = (float)fit->cut_floor;
+    a.p0 = dev_p0;
+    a.grad = dev_grad;
+    a.loss = dev_loss;
+    a.state = dev_state;
+    a.params = s->d_params;
+    a.params_out = dev_params;
+    a.losses = dev_losses;
+    a.cut = dev_cut;
+    RICH_HIP(launch_fit_step(a, stream));
+    PrepareArgs pa{s->d_segs, s->d_caps_static, s->d_params, s->d_caps, s->dev.n_caps, s->d_inst, s->dev.n_inst,
+                   s->d_nodes, s->n_top};
+    RICH_HIP(launch_prepare(pa, stream));
+    return RICH_OK;
+}
+
 rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,
                            uint64_t first_photon_id, const rich_outputs *out, hipStream_t stream) {
     if (!s || !src) return set_error(RICH_EINVAL, "scene and source must not be NULL");

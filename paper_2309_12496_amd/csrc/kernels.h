@@ -52,4 +52,21 @@ struct FilmArgs {
 hipError_t launch_film(const FilmArgs &a, const uint8_t *fate, const float *uv, uint64_t n, float *image,
                        uint8_t *hits, hipStream_t st);
 
+// One step of the alignment fit's optimiser (Adam with a cosine step size).
+struct FitArgs {
+    int32_t n_par;          // 6 x segments
+    int32_t n_steps;        // schedule length
+    double lr, lr_final, beta1, beta2, eps;
+    float scale[6];         // column normalisation
+    int32_t free[6];        // fitted columns
+    float outlier_cut, cut_floor;
+    const float *p0, *grad, *loss;
+    float *state;           // z [n_par], m [n_par], v [n_par], steps taken
+    float *params;          // the scene's parameter array
+    float *params_out;      // optional copy
+    float *losses;          // optional loss record [n_steps]
+    float *cut;             // optional residual cut
+};
+hipError_t launch_fit_step(const FitArgs &a, hipStream_t st);
+
 }  // namespace rich

@@ -119,6 +119,12 @@ class rich_film(C.Structure):
                 ("sigma", C.c_double), ("threshold", C.c_double)]
 
 
+class rich_fit(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("reserved", C.c_int32), ("lr", C.c_double), ("lr_final", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("scale", C.c_double * 6),
+                ("free", C.c_int32 * 6), ("outlier_cut", C.c_double), ("cut_floor", C.c_double)]
+
+
 class rich_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
 
@@ -138,18 +144,20 @@ _L.rich_propagate_adjoint.argtypes = [C.c_void_p, C.POINTER(rich_source), C.POIN
 _L.rich_get_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
 _L.rich_film_readout.argtypes = [C.POINTER(rich_film), C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                  C.c_void_p]
+_L.rich_fit_step.argtypes = [C.c_void_p, C.POINTER(rich_fit)] + [C.c_void_p] * 8
 _L.rich_cherenkov_yield.argtypes = [C.POINTER(rich_dispersion), C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.POINTER(C.c_double)]
 _L.rich_last_error.restype = C.c_char_p
 _L.rich_version.restype = C.c_char_p
 for _f in ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params", "rich_propagate",
            "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_get_status",
-           "rich_cherenkov_yield", "rich_film_readout"):
+           "rich_cherenkov_yield", "rich_film_readout", "rich_fit_step"):
     getattr(_L, _f).restype = C.c_int32
 
 EXPORTED = ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params",
             "rich_propagate", "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint",
-            "rich_get_status", "rich_cherenkov_yield", "rich_film_readout", "rich_last_error", "rich_version")
+            "rich_get_status", "rich_cherenkov_yield", "rich_film_readout", "rich_fit_step", "rich_last_error",
+            "rich_version")
 
 
 def _check(code):
@@ -220,6 +228,18 @@ def rich_propagate_adjoint(handle, source, batch, n_photons, seed, first_photon_
                                      int(first_photon_id), _ptr(dev_grad_uv), _ptr(dev_targets), _ptr(dev_mask),
                                      _ptr(dev_residual_cut), _ptr(dev_grad_params), _ptr(dev_loss),
                                      _stream(stream)))
+
+
+def rich_fit_step(handle, fit, dev_p0, dev_grad, dev_loss, dev_state, dev_params, dev_losses, dev_cut, stream=None):
+    _check(_L.rich_fit_step(handle, C.byref(fit), _ptr(dev_p0), _ptr(dev_grad), _ptr(dev_loss), _ptr(dev_state),
+                            _ptr(dev_params), _ptr(dev_losses), _ptr(dev_cut), _stream(stream)))
+
+
+def fit_config(steps, lr, lr_final, scale, free, betas=(0.9, 0.999), eps=1e-12, outlier_cut=0.0, cut_floor=0.0):
+    """rich_fit struct for rich_fit_step."""
+    return rich_fit(int(steps), 0, float(lr), float(lr_final), float(betas[0]), float(betas[1]), float(eps),
+                    (C.c_double * 6)(*[float(x) for x in scale]), (C.c_int32 * 6)(*[1 if f else 0 for f in free]),
+                    float(outlier_cut), float(cut_floor))
 
 
 def rich_cherenkov_yield(dispersion, n_radiator, beta, lambda_min, lambda_max):

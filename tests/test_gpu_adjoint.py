@@ -332,3 +332,77 @@ def test_adjoint_with_nothing_to_differentiate(R):
     torch.cuda.synchronize()
     assert not to_np(g).any()
     assert gs.status() == 0
+
+
+def test_fit_step_matches_oracle_adam(R, orc):
+    """rich_fit_step over 60 seeded gradient and loss steps (two with no photon counted) against the
+    oracle's FP64 Adam: moments, normalised coordinates, parameters, loss record, residual cut and
+    the parameters left in the scene."""
+    import torch
+    from paper_2309_12496_amd.align import PARAM_SCALE
+    scene = I.scene_g4()
+    gs = R.Scene(scene)
+    nseg = gs.n_segments
+    rng = np.random.default_rng(41)
+    T = 60
+    grads = (rng.normal(size=(T, nseg, 6)) * 10.0 ** rng.uniform(-2, 2, size=(T, nseg, 6))).astype(np.float32)
+    losses = rng.uniform(0.1, 10.0, size=T).astype(np.float32)
+    losses[[5, 17]] = 0.0
+    p0 = np.array(scene["params"], np.float32)
+    free = (True, True, True, False, True, False)
+    lr, lrf = 0.3, 1e-3
+    ref = orc.adam_fit_steps(p0.astype(np.float64), grads.astype(np.float64), losses.astype(np.float64), T, lr, lrf,
+                             PARAM_SCALE, free, outlier_cut=5.0, cut_floor=1e-3)
+    cfg = R.fit_config(T, lr, lrf, PARAM_SCALE, free, outlier_cut=5.0, cut_floor=1e-3)
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    p0_d, grad_d, loss_d = dev(p0), torch.empty((nseg, 6), device="cuda"), torch.empty(1, device="cuda")
+    n_par = 6 * nseg
+    state = torch.zeros(3 * n_par + 1, device="cuda")
+    params = torch.empty((nseg, 6), device="cuda")
+    rec = torch.zeros(T, device="cuda")
+    cut = torch.full((1,), float("inf"), device="cuda")
+    sc = np.asarray(PARAM_SCALE)
+    # FP32 error scales: a moment's rounding is relative to the running mean of |g| (m itself can cancel
+    # to ~0), and every step adds an error of ~1e-6 of its step size to z
+    gabs = np.zeros((nseg, 6))
+    cum = 0.0
+    for t in range(T):
+        g = np.where(np.asarray(free), grads[t].astype(np.float64) * sc, 0.0)
+        gabs = 0.9 * gabs + 0.1 * np.abs(g)
+        cum += lrf + 0.5 * (lr - lrf) * (1 + np.cos(np.pi * t / T))
+        grad_d.copy_(dev(grads[t]))
+        loss_d.fill_(float(losses[t]))
+        R.rich_fit_step(gs.handle, cfg, p0_d, grad_d, loss_d, state, params, rec, cut)
+        st = to_np(state).astype(np.float64)
+        z, m, v = (st[k * n_par:(k + 1) * n_par].reshape(nseg, 6) for k in range(3))
+        assert st[-1] == t + 1
+        assert np.all(np.abs(m - ref["m"][t]) <= 1e-5 * gabs + 1e-30), t
+        np.testing.assert_allclose(v, ref["v"][t], rtol=2e-5, atol=1e-30)
+        ztol = 1e-5 * cum + 1e-6 * np.abs(ref["z"][t])
+        assert np.all(np.abs(z - ref["z"][t]) <= ztol), (t, float((np.abs(z - ref["z"][t]) / ztol).max()))
+        tol = ztol * sc + np.spacing(np.abs(p0))    # z's tolerance, then FP32 rounding of p
+        err = np.abs(to_np(params) - ref["params"][t])
+        assert np.all(err <= tol), (t, float((err / tol).max()))
+        c = float(to_np(cut)[0])
+        assert (np.isinf(c) and np.isinf(ref["cut"][t])) or abs(c - ref["cut"][t]) <= 1e-6 * ref["cut"][t]
+    assert np.array_equal(to_np(rec), losses)
+    # the scene holds the last parameters: propagating it equals propagating after setting them
+    src = I.batch_source(I.sample_tracks(np.random.default_rng(1004), 200), np.full(200, 100))
+    a = to_np(R.propagate_batch(gs, src, 7, tune=R.tuning(256, 256, 4))["hit_uv"])
+    gs.set_params(params.clone())
+    b = to_np(R.propagate_batch(gs, src, 7, tune=R.tuning(256, 256, 4))["hit_uv"])
+    assert np.array_equal(a, b, equal_nan=True)
+    # argument checks
+    for bad in (R.fit_config(0, lr, lrf, PARAM_SCALE, free), R.fit_config(T, lr, lrf, PARAM_SCALE, free, betas=(1.0, 0.9)),
+                R.fit_config(T, lr, lrf, (0.0,) + tuple(PARAM_SCALE[1:]), free),
+                R.fit_config(T, float("nan"), lrf, PARAM_SCALE, free)):
+        with pytest.raises(R.RichError) as e:
+            R.rich_fit_step(gs.handle, bad, p0_d, grad_d, loss_d, state, None, None, None)
+        assert e.value.code == R.RICH_EINVAL
+    with pytest.raises(R.RichError) as e:
+        R.rich_fit_step(gs.handle, cfg, None, grad_d, loss_d, state, None, None, None)
+    assert e.value.code == R.RICH_EINVAL
+    plain = R.Scene(I.scene_coincident(True))
+    with pytest.raises(R.RichError) as e:
+        R.rich_fit_step(plain.handle, cfg, p0_d, grad_d, loss_d, state, None, None, None)
+    assert e.value.code == R.RICH_ESTATE
