@@ -21,16 +21,15 @@ class MirrorAlign(torch.autograd.Function):
         scene.set_params(params.detach())
         out = R.propagate(scene, src, n, seed)
         fate = out["fate"]
+        ctx.mark_non_differentiable(fate)
         ctx.scene, ctx.src, ctx.n, ctx.seed = scene, src, n, seed
-        ctx.save_for_backward(fate)
         return out["hit_uv"], fate
 
     @staticmethod
     def backward(ctx, grad_uv, grad_fate):
-        (fate,) = ctx.saved_tensors
-        on = (fate == R.DETECTED) | (fate == R.QE_REJECTED)
-        g = torch.where(on[:, None], grad_uv, torch.zeros_like(grad_uv)).nan_to_num(0.0)
-        grad, _ = R.adjoint(ctx.scene, ctx.src, ctx.seed, n=ctx.n, grad_uv=g, mask=on.to(torch.uint8))
+        # the adjoint reads the upstream gradient only for photons that reach the
+        # pixel grid, so the NaN hits of the others never enter the sum
+        grad, _ = R.adjoint(ctx.scene, ctx.src, ctx.seed, n=ctx.n, grad_uv=grad_uv)
         return grad, None, None, None, None
 
 

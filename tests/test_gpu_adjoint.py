@@ -156,7 +156,7 @@ def test_autograd_function_matches_fused_mode(R, c4small):
     loss = ((uv[use] - tgt[use]) ** 2).sum() / use.sum()
     loss.backward()
     gref, lref = R.adjoint(gs, src, p["seed"], n=cnt, targets=tgt.nan_to_num(0.0), mask=use.to(torch.uint8))
-    assert abs(float(loss) - float(lref)) <= 1e-5 * abs(float(lref))
+    assert abs(float(loss.detach()) - float(lref)) <= 1e-5 * abs(float(lref))
     grad_close(params.grad.cpu().numpy(), to_np(gref), rtol=1e-5, label="autograd")
 
 
