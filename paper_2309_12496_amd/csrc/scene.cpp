@@ -7,6 +7,9 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <atomic>
+#include <algorithm>
 
 #include "bvh_build.h"
 #include "kernels.h"
@@ -238,10 +241,41 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     std::vector<BuildBox> world_boxes(inst.size());
     std::vector<uint32_t> roots(inst.size());
     int max_inst_depth = 0;
+    // instance BVHs are independent: build them on host threads into their own
+    // arrays, then concatenate in instance order with node and triangle
+    // offsets rebased, which gives the same arrays as building them in turn
+    std::vector<std::vector<Node4>> knodes(inst.size());
+    std::vector<std::vector<Tri>> ktris(inst.size());
+    std::vector<int> kdepth(inst.size(), 0);
+    std::vector<BuildBox> kbox(inst.size());
+    {
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (size_t k; (k = next.fetch_add(1)) < inst.size();)
+                roots[k] = build_mesh_bvh4(inst[k].tris, knodes[k], ktris[k], &kdepth[k], &kbox[k]);
+        };
+        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t n_threads = std::min<size_t>({inst.size(), hw, 16});
+        std::vector<std::thread> pool;
+        for (size_t i = 1; i < n_threads; ++i) pool.emplace_back(work);
+        work();
+        for (auto &th : pool) th.join();
+    }
     for (size_t k = 0; k < inst.size(); ++k) {
-        int depth = 0;
-        BuildBox lb;
-        roots[k] = build_mesh_bvh4(inst[k].tris, inst_nodes, tris, &depth, &lb);
+        const uint32_t node_base = (uint32_t)inst_nodes.size(), tri_base = (uint32_t)tris.size();
+        for (Node4 nd : knodes[k]) {
+            for (int c = 0; c < 4; ++c) {
+                if (nd.child[c] == kEmpty) continue;
+                nd.child[c] += (nd.child[c] & kLeafBit) ? tri_base : node_base;   // leaf: first triangle (< 2^27)
+            }
+            inst_nodes.push_back(nd);
+        }
+        tris.insert(tris.end(), ktris[k].begin(), ktris[k].end());
+        std::vector<Node4>().swap(knodes[k]);
+        std::vector<Tri>().swap(ktris[k]);
+        roots[k] += node_base;
+        const int depth = kdepth[k];
+        const BuildBox &lb = kbox[k];
         max_inst_depth = std::max(max_inst_depth, depth);
         Instance &h = hinst[k];
         std::memset(&h, 0, sizeof h);
