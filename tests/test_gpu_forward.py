@@ -462,3 +462,21 @@ def test_closed_triangle_box_is_watertight(R, orc):
     out = R.propagate(gs, src, m, 3)
     assert not (to_np(out["fate"]) == R.ESCAPED).any()
     compare(out, orc.propagate(sc, src, m, 3), label="closed box")
+    # grazing photons: within 1 mm of a wall, 1e-7..1e-2 rad off parallel to it, and photons aimed
+    # at the lines where two walls meet
+    lo, hi = np.asarray(I.BOX_LO, float), np.asarray(I.BOX_HI, float)
+    ax, side = rng.integers(0, 3, m), rng.integers(0, 2, m)
+    o = rng.uniform(lo + 10, hi - 10, size=(m, 3))
+    o[np.arange(m), ax] = np.where(side == 1, hi[ax], lo[ax]) + np.where(side == 1, -1, 1) * rng.uniform(1e-3, 1, m)
+    d = rng.normal(size=(m, 3))
+    d[np.arange(m), ax] = 0
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d[np.arange(m), ax] = np.where(side == 1, 1, -1) * np.tan(10 ** rng.uniform(-7, -2, m))
+    e = rng.integers(0, 3, m)
+    corner = np.where(rng.integers(0, 2, (m, 3)) == 1, hi, lo).astype(float)
+    corner[np.arange(m), e] = rng.uniform(lo[e], hi[e])
+    o2 = rng.uniform(lo + 10, hi - 10, size=(m, 3))
+    for oo, dd in ((o, d), (o2, corner - o2)):
+        dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
+        out = R.propagate(gs, I.explicit_source(oo, dd, np.full(m, 400.0)), m, 3)
+        assert not (to_np(out["fate"]) == R.ESCAPED).any()
