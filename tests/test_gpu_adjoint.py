@@ -406,3 +406,25 @@ def test_fit_step_matches_oracle_adam(R, orc):
     with pytest.raises(R.RichError) as e:
         R.rich_fit_step(plain.handle, cfg, p0_d, grad_d, loss_d, state, None, None, None)
     assert e.value.code == R.RICH_ESTATE
+
+
+def test_prefiltered_source_gradient_matches_oracle(R, orc):
+    """Fused-loss adjoint with the paper's pre-propagation efficiency filter: rejected photons do
+    not count, kept ones are retraced with the surface roulettes off; loss and gradient match the
+    oracle's."""
+    scene = I.scene_g4()
+    rng = np.random.default_rng(1004)
+    src = I.with_prefilter(I.batch_source(I.sample_tracks(rng, 100), np.full(100, 1000)))
+    n, seed = 100_000, I.SEED_BASE + 4
+    target = orc.propagate(orc.Scene(scene, params=I.perturbed_params(4, scene)), src, n, seed)
+    cur = orc.propagate(orc.Scene(scene), src, n, seed, jacobian=True)
+    on = lambda r: np.isin(r["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    mask = on(target) & on(cur) & (target["edge_margin"] > 0.05) & (cur["edge_margin"] > 0.05)
+    assert (cur["fate"] == orc.PREFILTERED).mean() > 0.5
+    loss_ref, grad_ref, nuse = orc.mse_loss_and_grad(cur, target["hit_uv"], mask, scene["params"].shape[0])
+    assert nuse > 500
+    gs = R.Scene(scene)
+    grad, loss = R.adjoint(gs, src, seed, targets=np.nan_to_num(target["hit_uv"]), mask=mask)
+    assert abs(float(loss) / loss_ref - 1) < 1e-4
+    grad_close(to_np(grad), grad_ref, label="pre-filtered")
+    assert gs.status() == 0
