@@ -25,7 +25,8 @@
  *     rich_last_error() returns a thread-local message for the last failure.
  *   - Argument checks are synchronous; the propagation work is enqueued on
  *     the given stream and returns immediately.  Flags raised on the device
- *     (hit-list or traversal-stack overflow) are read by rich_get_status.
+ *     (hit-list or traversal-stack overflow, a batch size that is not the
+ *     tracks' photon total) are read by rich_get_status.
  *   - NULL output pointers mean "do not write".  The histogram, fate counts
  *     and hit-list counter accumulate: the caller zeroes them.
  *   - Launches on one scene share small device counters (the batch work
@@ -68,6 +69,7 @@ typedef int32_t rich_status;
 #define RICH_FLAG_HITLIST_OVERFLOW 0x1u
 #define RICH_FLAG_STACK_OVERFLOW   0x2u
 #define RICH_FLAG_PATH_OVERFLOW    0x4u   /* adjoint: more surfaces than it records */
+#define RICH_FLAG_BATCH_SIZE       0x8u   /* batch: n_photons differs from offsets[n_tracks] */
 
 #define RICH_MAX_TABLE 32           /* nodes of a piecewise-linear efficiency table */
 #define RICH_MAX_SEGMENTS 256       /* parametrised mirror segments */
@@ -303,7 +305,9 @@ rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipSt
 rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,
                            uint64_t first_photon_id, const rich_outputs *out, hipStream_t stream);
 
-/* Propagate every photon of a batch (n_photons = offsets[n_tracks]) in one
+/* Propagate every photon of a batch (n_photons = offsets[n_tracks], else
+ * the device raises RICH_FLAG_BATCH_SIZE; ids n_photons.. are then left out,
+ * or photons beyond the last track's count are drawn from it) in one
  * persistent launch replayed from a captured HIP graph.  tune = NULL picks the
  * launch shape with the autotuner (cached per scene and in the JSON file named
  * by RICH_TUNE_CACHE, if set; tuning synchronises the stream).  The call

@@ -337,7 +337,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
                     for (int rep = 0; rep < 3 && st == RICH_OK; ++rep) {
                         hipError_t r1 = launch_fill_u64(counter, 1, nullptr);
                         (void)hipEventRecord(a, nullptr);
-                        hipError_t r2 = launch_batch(s->dev, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), nullptr);
+                        hipError_t r2 = launch_batch(s->dev, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), false, nullptr);
                         (void)hipEventRecord(b, nullptr);
                         if (r1 != hipSuccess || r2 != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
                             st = set_error(RICH_EDEVICE, "autotune launch failed");
@@ -542,7 +542,7 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
             RICH_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = launch_fill_u64(s->d_counter, 1, s->capture_stream);
             hipError_t e2 = launch_batch(s->dev, ds, dout, n_photons, seed, s->d_counter, t.block, t.chunk,
-                                         grid_of(s, t), s->capture_stream);
+                                         grid_of(s, t), true, s->capture_stream);
             hipGraph_t gr = nullptr;
             hipError_t e3 = hipStreamEndCapture(s->capture_stream, &gr);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {

@@ -413,7 +413,8 @@ constexpr int kWaveGroup = 256;   // photons a batch wave regroups by cone azimu
 // Held to 128 VGPRs (4 waves per SIMD; 12 bytes of spills per lane): left
 // alone the compiler takes a few more registers and a wave less.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(
-    DevScene S, DevSource src, DevOutputs out, uint64_t n, uint64_t seed, unsigned long long *counter, int chunk) {
+    DevScene S, DevSource src, DevOutputs out, uint64_t n, uint64_t seed, unsigned long long *counter, int chunk,
+    int whole_batch) {
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
@@ -422,6 +423,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
                       (size_t)wave * (kWaveGroup + 64);
     uint32_t *wbins = wperm + kWaveGroup;
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
+    if (whole_batch && blockIdx.x == 0 && threadIdx.x == 0 && src.offsets[src.n_tracks] != n)
+        atomicOr(S.status, 8u);  // RICH_FLAG_BATCH_SIZE: n is not the photon total of the tracks
     while (true) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(counter, (unsigned long long)chunk);
@@ -481,9 +484,10 @@ size_t batch_lds_bytes(int block) {
 }
 
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
-                        unsigned long long *counter, int block, int chunk, int grid, hipStream_t st) {
+                        unsigned long long *counter, int block, int chunk, int grid, bool whole_batch, hipStream_t st) {
     size_t lds = batch_lds_bytes(block);
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk);
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk,
+                       whole_batch ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ _L = C.CDLL(LIB_PATH)
 RICH_OK, RICH_EINVAL, RICH_ENOMEM, RICH_EDEVICE, RICH_ERANGE, RICH_EOVERFLOW, RICH_ESTATE = 0, -1, -2, -3, -4, -5, -6
 DETECTED, QE_REJECTED, ABSORBED_MIRROR, ABSORBED, ESCAPED, MAX_BOUNCES, PREFILTERED = range(7)
 N_FATES = 7
-FLAG_HITLIST_OVERFLOW, FLAG_STACK_OVERFLOW, FLAG_PATH_OVERFLOW = 1, 2, 4
+FLAG_HITLIST_OVERFLOW, FLAG_STACK_OVERFLOW, FLAG_PATH_OVERFLOW, FLAG_BATCH_SIZE = 1, 2, 4, 8
 SRC_TRACK, SRC_EXPLICIT = 0, 2
 MAX_TABLE = 32
 

@@ -484,3 +484,22 @@ def test_closed_triangle_box_is_watertight(R, orc):
         dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
         out = R.propagate(gs, I.explicit_source(oo, dd, np.full(m, 400.0)), m, 3)
         assert not (to_np(out["fate"]) == R.ESCAPED).any()
+
+
+def test_batch_size_other_than_the_track_total_is_flagged(R, orc):
+    """n_photons below offsets[n_tracks]: the first n photons are traced as usual and the device
+    raises RICH_FLAG_BATCH_SIZE (read and cleared by rich_get_status); the whole batch raises nothing."""
+    cfg = I.config(3)
+    src = I.batch_source(cfg["source"]["tracks"][:50], np.full(50, 300))
+    gs = R.Scene(cfg["scene"])
+    b, keep, n = R.make_batch(src)
+    t, o = R.alloc_outputs(gs, n - 5)
+    R.rich_propagate_batch(gs.handle, b, n - 5, cfg["seed"], o, R.tuning(256, 256, 4))
+    assert gs.status() == R.FLAG_BATCH_SIZE
+    assert gs.status() == 0
+    ids = np.arange(0, n - 5, 11, dtype=np.uint64)
+    ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
+    sub = {k: to_np(t[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    compare(sub, ref, label="batch prefix")
+    out = R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(256, 256, 4))
+    assert gs.status() == 0 and int(to_np(out["fate_counts"]).sum()) == n
