@@ -30,6 +30,7 @@ N_FATES = 7
 FLAG_HITLIST_OVERFLOW, FLAG_STACK_OVERFLOW, FLAG_PATH_OVERFLOW, FLAG_BATCH_SIZE = 1, 2, 4, 8
 SRC_TRACK, SRC_EXPLICIT = 0, 2
 MAX_TABLE = 32
+MAX_SEGMENTS = 256
 
 _dp = C.POINTER(C.c_double)
 _d3 = C.c_double * 3

@@ -428,3 +428,54 @@ def test_prefiltered_source_gradient_matches_oracle(R, orc):
     assert abs(float(loss) / loss_ref - 1) < 1e-4
     grad_close(to_np(grad), grad_ref, label="pre-filtered")
     assert gs.status() == 0
+
+
+def test_largest_segment_count(R, orc):
+    """RICH_MAX_SEGMENTS (256) analytic segments, 1,536 parameters: more than one thread block's
+    worth in the fit step, the widest accumulator rows in the adjoint.  The fused-loss gradient and
+    five fit steps match the oracle."""
+    import torch
+    from paper_2309_12496_amd.align import PARAM_SCALE
+    cells = I.grid_cells(16, 16)
+    scene = I.scene_g1()
+    scene["segments"] = I._segments_for_cells(cells)
+    scene["params"] = I._nominal_params(len(cells))
+    scene["caps"] = I._caps_for_cells(cells, list(range(len(cells))))
+    assert len(cells) == R.MAX_SEGMENTS
+    rng = np.random.default_rng(1007)
+    src = I.batch_source(I.sample_tracks(rng, 200), np.full(200, 500))
+    n, seed = 100_000, I.SEED_BASE + 7
+    tp = I.perturbed_params(7, scene)
+    target = orc.propagate(orc.Scene(scene, params=tp), src, n, seed)
+    cur = orc.propagate(orc.Scene(scene), src, n, seed, jacobian=True)
+    on = lambda r: np.isin(r["fate"], [orc.DETECTED, orc.QE_REJECTED])
+    mask = on(target) & on(cur) & (target["edge_margin"] > 0.05) & (cur["edge_margin"] > 0.05)
+    loss_ref, grad_ref, nuse = orc.mse_loss_and_grad(cur, target["hit_uv"], mask, len(cells))
+    assert nuse > 1000 and np.count_nonzero(np.abs(grad_ref).sum(1)) > 8
+    gs = R.Scene(scene)
+    assert gs.n_segments == len(cells)
+    grad, loss = R.adjoint(gs, src, seed, targets=np.nan_to_num(target["hit_uv"]), mask=mask)
+    assert abs(float(loss) / loss_ref - 1) < 1e-4
+    grad_close(to_np(grad), grad_ref, label="256 segments")
+    # five fit steps on synthetic gradients, against the FP64 Adam
+    T = 5
+    gr = (rng.normal(size=(T, len(cells), 6))).astype(np.float32)
+    ls = rng.uniform(0.5, 2.0, size=T).astype(np.float32)
+    p0 = np.array(scene["params"], np.float32)
+    free = (True, True, True, False, False, False)
+    ref = orc.adam_fit_steps(p0.astype(np.float64), gr.astype(np.float64), ls.astype(np.float64), T, 0.3, 1e-3,
+                             PARAM_SCALE, free, outlier_cut=5.0, cut_floor=1e-3)
+    cfg = R.fit_config(T, 0.3, 1e-3, PARAM_SCALE, free, outlier_cut=5.0, cut_floor=1e-3)
+    p0_d = torch.as_tensor(p0, device="cuda")
+    state = torch.zeros(3 * p0.size + 1, device="cuda")
+    params = torch.empty_like(p0_d)
+    g_d, l_d, cut = torch.empty_like(p0_d), torch.empty(1, device="cuda"), torch.empty(1, device="cuda")
+    for t in range(T):
+        g_d.copy_(torch.as_tensor(gr[t], device="cuda"))
+        l_d.fill_(float(ls[t]))
+        R.rich_fit_step(gs.handle, cfg, p0_d, g_d, l_d, state, params, None, cut)
+    z = to_np(state)[:p0.size].reshape(p0.shape).astype(np.float64)
+    np.testing.assert_allclose(z, ref["z"][-1], rtol=1e-5, atol=1e-5)
+    assert to_np(state)[-1] == T
+    assert abs(float(to_np(cut)[0]) - ref["cut"][-1]) <= 1e-6 * ref["cut"][-1]
+    assert gs.status() == 0
