@@ -111,3 +111,34 @@ def test_dispersion_validation(R):
         with pytest.raises(R.RichError) as e:
             R.rich_propagate(gs.handle, s, 10, 1, 0, o)
         assert e.value.code == R.RICH_EINVAL, k
+
+
+def test_tables_at_the_largest_size(R, orc):
+    """Quantum efficiency, mirror reflectivity and dispersion tables of 32 nodes (the most a table
+    holds): every photon of the C1 workload against the oracle; a 33rd node is refused."""
+    import copy
+    cfg = I.config(1)
+    sc = copy.deepcopy(cfg["scene"])
+    lam = np.linspace(200.0, 600.0, R.MAX_TABLE)
+    sc["detector"]["qe_lambda"] = lam
+    sc["detector"]["qe_value"] = 0.35 * np.exp(-((lam - 420.0) / 90.0) ** 2)
+    sc["materials"][0]["refl_lambda"] = lam
+    sc["materials"][0]["refl_value"] = 0.9 + 0.05 * np.sin(lam / 40.0)
+    table = I.gas_dispersion(step_nm=400.0 / (R.MAX_TABLE - 1))
+    assert len(table["lambda"]) == R.MAX_TABLE
+    src = I.with_dispersion(cfg["source"], table)
+    gs = R.Scene(sc)
+    out = R.propagate(gs, src, 100_000, cfg["seed"])
+    ref = orc.propagate(sc, src, 100_000, cfg["seed"])
+    compare(out, ref, label="32-node tables")
+    big = copy.deepcopy(sc)
+    big["detector"]["qe_lambda"] = np.linspace(200.0, 600.0, R.MAX_TABLE + 1)
+    big["detector"]["qe_value"] = np.full(R.MAX_TABLE + 1, 0.3)
+    with pytest.raises(R.RichError) as e:
+        R.Scene(big)
+    assert e.value.code == R.RICH_EINVAL
+    long = I.with_dispersion(cfg["source"], I.gas_dispersion(step_nm=400.0 / R.MAX_TABLE))
+    assert len(long["dispersion"]["lambda"]) == R.MAX_TABLE + 1
+    with pytest.raises(R.RichError) as e:
+        R.propagate(gs, long, 10, cfg["seed"])
+    assert e.value.code == R.RICH_EINVAL
