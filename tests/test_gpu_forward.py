@@ -503,3 +503,28 @@ def test_batch_size_other_than_the_track_total_is_flagged(R, orc):
     compare(sub, ref, label="batch prefix")
     out = R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(256, 256, 4))
     assert gs.status() == 0 and int(to_np(out["fate_counts"]).sum()) == n
+
+
+def test_hit_list_with_regrouped_photons(R, c2):
+    """The compact hit list when photons are traced out of id order (regrouped by azimuth), from the
+    forward kernel on the meshed scene and from the persistent batch kernel: exactly the DETECTED
+    photons, each once, with their own pixel and position."""
+    import torch
+    cfg, gs, _ = c2
+    n = 300_000
+    runs = [R.propagate(gs, cfg["source"], n, cfg["seed"], hit_list_capacity=n)]
+    c3 = I.config(3)
+    src = I.batch_source(c3["source"]["tracks"][:300], np.full(300, 1000))
+    runs.append(R.propagate_batch(gs, src, cfg["seed"], tune=R.tuning(256, 256, 4), hit_list_capacity=300_000))
+    for out in runs:
+        torch.cuda.synchronize()
+        fate = to_np(out["fate"])
+        cnt = int(out["hit_count"][0])
+        det = np.flatnonzero(fate == 0)
+        assert cnt == len(det) > 1000
+        ids, pix, xyz = R.decode_hits(out["hit_list"], cnt)
+        order = np.argsort(ids)
+        assert np.array_equal(ids[order], det.astype(np.uint64))
+        assert np.array_equal(pix[order], to_np(out["pixel"])[det])
+        assert np.array_equal(xyz[order], to_np(out["hit_xyz"])[det])
+    assert gs.status() == 0
