@@ -528,3 +528,34 @@ def test_hit_list_with_regrouped_photons(R, c2):
         assert np.array_equal(pix[order], to_np(out["pixel"])[det])
         assert np.array_equal(xyz[order], to_np(out["hit_xyz"])[det])
     assert gs.status() == 0
+
+
+def test_side_stream_launches(R, c2):
+    """Forward, batch (graph replay) and adjoint launched on a non-default stream give the results of
+    the same calls on the default stream (all three are enqueued on the stream they are given)."""
+    import torch
+    cfg, gs, _ = c2
+    n = 200_000
+    ref = R.propagate(gs, cfg["source"], n, cfg["seed"])
+    c3 = I.config(3)
+    src = I.batch_source(c3["source"]["tracks"][:100], np.full(100, 1000))
+    tune = R.tuning(256, 256, 4)
+    ref_b = R.propagate_batch(gs, src, cfg["seed"], tune=tune)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        out = R.propagate(gs, cfg["source"], n, cfg["seed"], stream=side)
+        out_b = R.propagate_batch(gs, src, cfg["seed"], tune=tune, stream=side)
+    side.synchronize()
+    for a, b in ((out, ref), (out_b, ref_b)):
+        for k in ("fate", "pixel", "hit_xyz", "hit_time", "histogram", "fate_counts"):
+            assert np.array_equal(to_np(a[k]), to_np(b[k]), equal_nan=True), k
+    c4 = I.config(4)
+    g4 = R.Scene(c4["scene"])
+    tgt = np.zeros((c4["n_photons"], 2), np.float32)
+    g_ref, l_ref = R.adjoint(g4, c4["source"], c4["seed"], targets=tgt)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        g_s, l_s = R.adjoint(g4, c4["source"], c4["seed"], targets=tgt, stream=side)
+    side.synchronize()
+    assert np.array_equal(to_np(g_s), to_np(g_ref)) and float(l_s) == float(l_ref)
