@@ -307,7 +307,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     e = e == hipSuccess ? hipMalloc(&time, 4 * n_t) : e;
     e = e == hipSuccess ? hipMalloc(&hist, 4 * nh) : e;
     e = e == hipSuccess ? hipMalloc(&counts, 8 * RICH_N_FATES) : e;
-    e = e == hipSuccess ? hipMalloc(&counter, 8) : e;
+    e = e == hipSuccess ? hipMalloc(&counter, 8 * kBatchCounters) : e;
     hipEvent_t a = nullptr, b = nullptr;
     e = e == hipSuccess ? hipEventCreate(&a) : e;
     e = e == hipSuccess ? hipEventCreate(&b) : e;
@@ -335,7 +335,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
                     rich_tuning t{blk, ch, bpc, 0};
                     float tmin = INFINITY;
                     for (int rep = 0; rep < 3 && st == RICH_OK; ++rep) {
-                        hipError_t r1 = launch_fill_u64(counter, 1, nullptr);
+                        hipError_t r1 = launch_fill_u64(counter, kBatchCounters, nullptr);
                         (void)hipEventRecord(a, nullptr);
                         hipError_t r2 = launch_batch(s->dev, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), false, nullptr);
                         (void)hipEventRecord(b, nullptr);
@@ -540,7 +540,7 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
             }
             if (!s->capture_stream) RICH_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
             RICH_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e1 = launch_fill_u64(s->d_counter, 1, s->capture_stream);
+            hipError_t e1 = launch_fill_u64(s->d_counter, kBatchCounters, s->capture_stream);
             hipError_t e2 = launch_batch(s->dev, ds, dout, n_photons, seed, s->d_counter, t.block, t.chunk,
                                          grid_of(s, t), true, s->capture_stream);
             hipGraph_t gr = nullptr;

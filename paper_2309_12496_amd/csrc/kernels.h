@@ -23,7 +23,12 @@ hipError_t launch_prepare(const PrepareArgs &a, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st);
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n,
                           uint64_t first, uint64_t seed, int n_cu, hipStream_t st);
-// whole_batch: n is meant to be every photon of the tracks (flag raised if not)
+// Work counters of the batch kernel: one per id partition, a 128-byte line apart.
+constexpr int kBatchParts = 8;
+constexpr int kCounterStride = 16;
+constexpr int kBatchCounters = kBatchParts * kCounterStride;
+// whole_batch: n is meant to be every photon of the tracks (flag raised if not);
+// counter: kBatchCounters zeroed words
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, bool whole_batch, hipStream_t st);
 size_t batch_lds_bytes(int block);

@@ -414,7 +414,7 @@ constexpr int kWaveGroup = 256;   // photons a batch wave regroups by cone azimu
 // alone the compiler takes a few more registers and a wave less.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(
     DevScene S, DevSource src, DevOutputs out, uint64_t n, uint64_t seed, unsigned long long *counter, int chunk,
-    int whole_batch) {
+    int whole_batch, uint64_t part, int n_parts) {
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
     uint32_t *stk = lds_stack + threadIdx.x;
@@ -425,12 +425,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     if (whole_batch && blockIdx.x == 0 && threadIdx.x == 0 && src.offsets[src.n_tracks] != n)
         atomicOr(S.status, 8u);  // RICH_FLAG_BATCH_SIZE: n is not the photon total of the tracks
+    // The id range is cut into n_parts contiguous partitions of `part` ids
+    // (a multiple of the chunk); block b claims chunks of partition b mod
+    // n_parts from that partition's own counter.  Blocks are dispatched to the
+    // 8 XCDs round robin, so with 8 partitions each XCD works through its own
+    // run of tracks and its L2 holds their geometry only.
+    const int xp = (int)(blockIdx.x % (unsigned)n_parts);
+    unsigned long long *ctr = counter + kCounterStride * xp;
+    const uint64_t p_lo = (uint64_t)xp * part;
+    const uint64_t p_hi = min(p_lo + part, n);
     while (true) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(counter, (unsigned long long)chunk);
+        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)chunk);
         uint32_t lo = __shfl((uint32_t)base, 0), hi = __shfl((uint32_t)(base >> 32), 0);
-        base = ((unsigned long long)hi << 32) | lo;
-        if (base >= n) break;
+        base = p_lo + (((unsigned long long)hi << 32) | lo);
+        if (base >= p_hi) break;
         // With meshes (or the pre-filter), each kWaveGroup-photon slice of the
         // chunk is regrouped by cone azimuth (64 bins of the azimuth's
         // uniform; pre-filter rejects last) in this wave's own LDS region, so
@@ -486,8 +495,11 @@ size_t batch_lds_bytes(int block) {
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, bool whole_batch, hipStream_t st) {
     size_t lds = batch_lds_bytes(block);
+    const int n_parts = (grid >= kBatchParts && grid % kBatchParts == 0) ? kBatchParts : 1;
+    const uint64_t per = (n + n_parts - 1) / n_parts;
+    const uint64_t part = (per + chunk - 1) / chunk * chunk;
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk,
-                       whole_batch ? 1 : 0);
+                       whole_batch ? 1 : 0, part, n_parts);
     return hipGetLastError();
 }
 

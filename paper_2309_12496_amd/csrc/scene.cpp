@@ -398,11 +398,11 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     }
     std::vector<CapDev> zero_caps(d->n_caps);
     unsigned int zero_status = 0;
-    unsigned long long zero_counter = 0;
+    std::vector<unsigned long long> zero_counter(kBatchCounters, 0ull);
     std::vector<unsigned long long> zero_tally(kTallyWords, 0ull);
     if ((st = upload(&s->d_caps, zero_caps.data(), zero_caps.size(), &bytes)) ||
         (st = upload(&s->d_status, &zero_status, 1, &bytes)) ||
-        (st = upload(&s->d_counter, &zero_counter, 1, &bytes)) ||
+        (st = upload(&s->d_counter, zero_counter.data(), zero_counter.size(), &bytes)) ||
         (st = upload(&s->d_tally, zero_tally.data(), zero_tally.size(), &bytes))) {
         free_scene(s);
         (void)hipSetDevice(prev);
