@@ -134,7 +134,7 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
     sc = R.Scene(cfg["scene"])
     build_s = time.perf_counter() - t0
     b, keep, n = R.make_batch(cfg["source"])
-    tune = R.tuning(256, 256, 4)
+    tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])      # the launch shape a caller gets with tune=NULL
     sc.set_params(cfg["target_params"])
     tgt_out = R.propagate_batch(sc, cfg["source"], cfg["seed"], tune=tune)
     targets = tgt_out["hit_uv"].nan_to_num(0.0)
@@ -153,7 +153,8 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
     return {"workload": cfg["name"], "photons_per_step": n, "parameters": 6 * sc.n_segments,
             "forward_ms": s_ms, "adjoint_ms": a_ms, "ms_per_step": s_ms + a_ms,
             "photons_per_s": n / ((s_ms + a_ms) * 1e-3), "forward_photons_per_s": n / (s_ms * 1e-3),
-            "loss_mm2": float(loss), "masked_photons": int(mask.sum()), "scene_build_s": round(build_s, 3)}
+            "loss_mm2": float(loss), "masked_photons": int(mask.sum()), "scene_build_s": round(build_s, 3),
+            "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu}}
 
 
 def form_align_fit(R, I, stream, steps):
