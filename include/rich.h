@@ -316,8 +316,10 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
 rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
                                  const rich_outputs *out, const rich_tuning *tune, hipStream_t stream);
 
-/* Time the batch kernel over a grid of launch shapes on scratch outputs and
- * return the fastest (synchronous). */
+/* Time the batch kernel over a grid of launch shapes (block 64..512 threads,
+ * chunk 64..1024 ids, 1..16 resident blocks per CU as LDS allows) on the
+ * first min(n_photons, 4e6) photons, into scratch outputs, and return the
+ * fastest (synchronous; allocates and frees its scratch buffers). */
 rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
                           rich_tuning *out);
 
