@@ -140,7 +140,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
     uint64_t *queue = reinterpret_cast<uint64_t *>(acc_all + (size_t)waves * padded_width(a.n_par)) +
                       (size_t)wave * kAdjQueue;
 
-    const DetDev &det = *S.det;
+    const RICH_CONST DetDev &det = cref(*S.det);
     // Squared residual cut; a negative or NaN cut admits no photon.
     float cut2 = __builtin_inff();
     if (a.residual_cut) {

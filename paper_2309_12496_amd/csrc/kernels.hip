@@ -202,6 +202,10 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
 // Trace photon g (output slot i), write its results and return its fate (-1
 // for inactive lanes).  Every lane of the wave must call this together: the
 // hit list uses wave-wide ballots.
+// kConstDet: read the detector through the constant address space (scalar
+// loads).  The forward kernel gains from it; the batch kernel, held to 128
+// VGPRs, spills the extra scalar state and reads the detector per lane.
+template <bool kConstDet>
 __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
                                           uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride) {
     PathEnd end;
@@ -210,13 +214,17 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
     if (active) {
         Photon ph = make_photon(src, seed, g, i);
         NoRecord rec;
-        if (!src.prefilter) {
-            propagate(S, *S.det, ph, seed, g, stk, stride, end, rec);
-        } else if (prefilter_keep(S, *S.det, src, ph, seed, g)) {
-            propagate(S, *S.det, ph, seed, g, stk, stride, end, rec, false);
-        } else {
-            end.fate = kPrefiltered;
-        }
+        auto run = [&](const auto &det) {
+            if (!src.prefilter) {
+                propagate(S, det, ph, seed, g, stk, stride, end, rec);
+            } else if (prefilter_keep(S, det, src, ph, seed, g)) {
+                propagate(S, det, ph, seed, g, stk, stride, end, rec, false);
+            } else {
+                end.fate = kPrefiltered;
+            }
+        };
+        if constexpr (kConstDet) run(cref(*S.det));
+        else run(*S.det);
         bool on_det = end.fate == kDetected || end.fate == kQeRejected;
         if (out.fate) out.fate[i] = (uint8_t)end.fate;
         if (out.pixel) out.pixel[i] = on_det ? end.pixel : -1;
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
             uint64_t i = base + threadIdx.x;
-            int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+            int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
             if (out.fate_counts) tally_wave(cnt, fate);
         }
     } else {
@@ -379,7 +387,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
             __syncthreads();
             for (int j = 0; j < per; ++j) {
                 const uint64_t i = base + perm[j * kForwardBlock + threadIdx.x];
-                int fate = photon_job(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+                int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
                 if (out.fate_counts) tally_wave(cnt, fate);
             }
             __syncthreads();
@@ -476,7 +484,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
             for (int j = 0; j < group; j += 64) {
                 const uint32_t off = regroup ? wperm[j + lane] : (uint32_t)(j + lane);
                 const uint64_t g = base + (uint64_t)k + off;
-                int fate = photon_job(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+                int fate = photon_job<false>(S, src, out, g < n, g, g, seed, stk, blockDim.x);
                 if (out.fate_counts) tally_wave(cnt, fate);
             }
             if (regroup) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

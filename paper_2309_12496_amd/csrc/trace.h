@@ -33,6 +33,20 @@ __device__ __forceinline__ V3 mat3(const float *m, V3 v) {  // row-major 3x3 tim
 }
 __device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
 
+// Scene data (caps, rects, detector, materials and their tables) is never
+// written while a propagation kernel runs: the prepare kernel updates it in an
+// earlier launch.  Reading it through the constant address space tells the
+// compiler so, and reads at wave-uniform addresses (the loops over analytic
+// primitives and table nodes) become one scalar load per wave instead of one
+// vector load per lane.  Without it, any output store earlier in the kernel
+// keeps the compiler from proving the data unchanged.
+#define RICH_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const RICH_CONST T &cref(const T &x) {
+    return *(const RICH_CONST T *)&x;
+}
+__device__ __forceinline__ V3 ld3(const RICH_CONST float *p) { return V3{p[0], p[1], p[2]}; }
+
 // ---------------------------------------------------------------- Philox4x32-10
 
 // Counter-based generator of Salmon et al. (SC'11): ten rounds of two 32x32->64
@@ -67,7 +81,8 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // Piecewise-linear table with per-segment slopes, clamped outside its range.
 // The loop bound and the node addresses are uniform, so the nodes arrive
 // through scalar loads and each lane only selects.
-__device__ __forceinline__ float lerp_table(int n, const float *x, const float *y, const float *sl, float l) {
+template <class P>   // const float * or const RICH_CONST float *
+__device__ __forceinline__ float lerp_table(int n, P x, P y, P sl, float l) {
     float v = l <= x[0] ? y[0] : y[n - 1];
     for (int j = 0; j + 1 < n; ++j) {
         float xa = x[j];
@@ -278,7 +293,7 @@ __device__ __forceinline__ bool better(float t, uint32_t prim, const Hit &h) {
 
 // Sphere cap with the cancellation-free discriminant of Haines et al.
 // (Ray Tracing Gems, ch. 7): disc = R^2 - |f - (f.d) d|^2, roots q and c/q.
-__device__ __forceinline__ bool hit_cap(const CapDev &cp, V3 o, V3 d, float tmin, float &t_out, int &root) {
+__device__ __forceinline__ bool hit_cap(const RICH_CONST CapDev &cp, V3 o, V3 d, float tmin, float &t_out, int &root) {
     V3 C = ld3(cp.C);
     V3 f = o - C;
     float b = dot(f, d);
@@ -483,7 +498,8 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
     }
 }
 
-__device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det, V3 o, V3 d, Hit &h, uint32_t *stk,
+template <class D>
+__device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 o, V3 d, Hit &h, uint32_t *stk,
                                             int stride) {
     h.t = INFINITY;
     h.prim = 0xFFFFFFFFu;
@@ -495,7 +511,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det
     ray_setup(r, o, d);
     float t;
     for (int i = 0; i < S.n_caps; ++i) {
-        const CapDev &cp = S.caps[i];
+        const RICH_CONST CapDev &cp = cref(S.caps[i]);
         if (slab_entry(r, cp.lo[0], cp.lo[1], cp.lo[2], cp.hi[0], cp.hi[1], cp.hi[2], h.t) == INFINITY) continue;
         int root;
         if (hit_cap(cp, o, d, tmin, t, root) && better(t, (uint32_t)i, h)) {
@@ -505,7 +521,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det
         }
     }
     for (int i = 0; i < S.n_rects; ++i) {
-        const RectDev &rc = S.rects[i];
+        const RICH_CONST RectDev &rc = cref(S.rects[i]);
         if (hit_plane_rect(ld3(rc.c), ld3(rc.n), ld3(rc.u), ld3(rc.v), rc.hu, rc.hv, o, d, tmin, t) &&
             better(t, (uint32_t)(S.n_caps + i), h)) {
             h.t = t;
@@ -529,7 +545,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const DetDev &det
 __device__ __forceinline__ float reflectivity(const DevScene &S, int mat, float lambda) {
     float v = 0.0f;
     for (int m = 0; m < S.n_mats; ++m) {
-        const MatDev &M = S.mats[m];
+        const RICH_CONST MatDev &M = cref(S.mats[m]);
         if (M.kind != 0) continue;
         float r = lerp_table(M.n, M.x, M.y, M.s, lambda);
         v = (mat == m) ? r : v;
@@ -577,7 +593,8 @@ constexpr int kPrefiltered = 6;
 
 // Pre-propagation efficiency filter: keep the photon with probability
 // QE(lambda) * prod_k refl_k(lambda), as one accept-reject per photon.
-__device__ __forceinline__ bool prefilter_keep(const DevScene &S, const DetDev &det, const DevSource &src,
+template <class D>
+__device__ __forceinline__ bool prefilter_keep(const DevScene &S, const D &det, const DevSource &src,
                                                const Photon &ph, uint64_t seed, uint64_t g) {
     float p = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
     for (int k = 0; k < src.pf_n; ++k) p *= reflectivity(S, src.pf_mats[k], ph.lambda);
@@ -586,8 +603,8 @@ __device__ __forceinline__ bool prefilter_keep(const DevScene &S, const DetDev &
 
 // Trace one photon.  With `efficiencies` false (photons kept by the
 // pre-filter) mirrors always reflect and the detector always detects.
-template <class Rec>
-__device__ __forceinline__ void propagate(const DevScene &S, const DetDev &det, const Photon &ph, uint64_t seed,
+template <class D, class Rec>
+__device__ __forceinline__ void propagate(const DevScene &S, const D &det, const Photon &ph, uint64_t seed,
                                           uint64_t g, uint32_t *stk, int stride, PathEnd &end, Rec &rec,
                                           bool efficiencies = true) {
     V3 o = ph.o, d = ph.d;
