@@ -36,14 +36,14 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 # VALU work per photon of forward_kernel on the headline workload, in 32-bit
-# lane operations: SQ_INSTS_VALU x 64 lanes / photons = 1.10180e9 x 64 / 1e7
+# lane operations: SQ_INSTS_VALU x 64 lanes / photons = 1.10301e9 x 64 / 1e7
 # (profiles/forward_kernel_c2_counters.md).  Issued slots, inactive lanes included.
-ALU_OPS_PER_PHOTON = 7051.5
+ALU_OPS_PER_PHOTON = 7059.3
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
 # KiB per dispatch, scaled by the 256 MiB copy-kernel calibration, / 1e7 photons.
-TRAFFIC_BYTES_PER_PHOTON = (1065.81 * 1.9998 + 1175596.8) * 1024 / 1e7
+TRAFFIC_BYTES_PER_PHOTON = (1064.52 * 1.9998 + 1177078.5) * 1024 / 1e7
 
 
 def parse():

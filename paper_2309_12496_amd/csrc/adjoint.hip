@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
         float gu = 0.0f, gv = 0.0f, loss = 0.0f, cnt = 0.0f;
         if (act) {
             uint64_t g = first + i;
-            Photon ph = make_photon(src, seed, g, i);
+            Photon ph = make_photon(src, seed, g, i, false);
             if (!src.prefilter) {
                 propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec);
             } else if (prefilter_keep(S, det, src, ph, seed, g)) {

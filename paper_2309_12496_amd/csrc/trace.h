@@ -133,6 +133,23 @@ __device__ __forceinline__ int find_track(const uint64_t *off, int n_tracks, uin
     return lo;
 }
 
+// Track of photon g when the wave's photons mostly share one: a scalar
+// binary search (constant address space, wave-uniform index) for the wave's
+// first active photon, and the per-lane search only for lanes outside that
+// track's id range.
+__device__ __forceinline__ int find_track_wave(const uint64_t *off, int n_tracks, uint64_t g) {
+    const RICH_CONST uint64_t *oc = (const RICH_CONST uint64_t *)off;
+    const uint64_t g0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g >> 32)) << 32) |
+                        __builtin_amdgcn_readfirstlane((uint32_t)g);
+    int lo = 0, hi = n_tracks;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (oc[mid] <= g0) lo = mid; else hi = mid;
+    }
+    if (g >= oc[lo] && g < oc[lo + 1]) return lo;
+    return find_track(off, n_tracks, g);
+}
+
 // Orthonormal basis (b1, b2) around unit n, after Duff et al., JCGT 2017.
 __device__ __forceinline__ void basis(V3 n, V3 &b1, V3 &b2) {
     float sgn = copysignf(1.0f, n.z);
@@ -142,7 +159,11 @@ __device__ __forceinline__ void basis(V3 n, V3 &b1, V3 &b2) {
     b2 = V3{b, sgn + n.y * n.y * a, -n.y};
 }
 
-__device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t seed, uint64_t g, uint64_t i) {
+// wave_track: the wave's photons come from consecutive ids (forward and batch
+// kernels), so most lanes share the first lane's track; the adjoint's queued
+// photons do not, and search per lane.
+__device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t seed, uint64_t g, uint64_t i,
+                                              bool wave_track = true) {
     uint4 w = photon_block(seed, g, 0);
     Photon ph;
     ph.u_qe = u24(w.w);
@@ -158,7 +179,7 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
     V3 P0, T, E1, E2;
     float L, ct, st, beta;
     if (src.kind == 1) {
-        int k = find_track(src.offsets, src.n_tracks, g);
+        int k = wave_track ? find_track_wave(src.offsets, src.n_tracks, g) : find_track(src.offsets, src.n_tracks, g);
         const float4 *tr = reinterpret_cast<const float4 *>(src.tracks) + 2 * k;
         float4 a = tr[0], b = tr[1];
         P0 = V3{a.x, a.y, a.z};
