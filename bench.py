@@ -232,7 +232,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: photons shard by id range across GPUs, "
-              "but this build measures a single MI355X (use --gpus 1).", file=sys.stderr)
+              "but this benchmark measures a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
