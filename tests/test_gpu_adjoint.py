@@ -170,6 +170,9 @@ def test_c4_full_size_gradient(R, orc):
     assert abs(float(loss) / p["loss"] - 1) < 1e-4
     rel, worst = grad_close(to_np(grad), p["grad"], label="C4 full")
     print({"nuse": p["nuse"], "rel": rel, "worst": worst})
+    # the forward of every photon at the autotuned launch shape the benchmark times
+    out = R.propagate_batch(gs, p["src"], p["seed"])
+    compare(out, p["cur"], label="C4 forward, autotuned shape")
 
 
 def test_meshed_segments_forward_and_gradient(R, orc):
