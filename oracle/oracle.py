@@ -62,8 +62,11 @@ class Outputs(C.Structure):
     _fields_ = [
         ("fate", C.POINTER(C.c_uint8)), ("pixel", _ip), ("hit_xyz", _dp), ("hit_uv", _dp),
         ("edge_margin", _dp), ("pixel_margin", _dp), ("roulette_margin", _dp), ("n_bounce", _ip), ("segment", _ip), ("jac", _dp),
-        ("hit_time", _dp),
+        ("hit_time", _dp), ("segments", _ip), ("jacs", _dp),
     ]
+
+
+MAX_PATH_SEGS = 4   # ORC_MAX_PATH_SEGS
 
 
 class Film(C.Structure):
@@ -339,8 +342,12 @@ def propagate(scene, src, n, seed, first_id=0, use_bvh=True, jacobian=False, thr
     if jacobian:
         res["segment"] = np.zeros(n, np.int32)
         res["jac"] = np.zeros((n, 2, 6))
+        res["segments"] = np.zeros((n, MAX_PATH_SEGS), np.int32)
+        res["jacs"] = np.zeros((n, MAX_PATH_SEGS, 2, 6))
         o.segment = _ptr(res["segment"], C.c_int32)
         o.jac = _ptr(res["jac"], C.c_double)
+        o.segments = _ptr(res["segments"], C.c_int32)
+        o.jacs = _ptr(res["jacs"], C.c_double)
     if threads is None:
         threads = min(os.cpu_count() or 1, 16)
     bvh = 1 if (use_bvh and scene.has_bvh) else 0
@@ -392,25 +399,28 @@ def mse_loss_and_grad(res, targets, mask, n_seg, residual_cut=None):
 
     L = (1/N) sum_i |uv_i - target_i|^2 over photons in ``mask`` that reach the
     detector (and, given ``residual_cut``, whose |uv_i - target_i| does not
-    exceed it); dL/dp = (2/N) sum_i J_i^T (uv_i - target_i) scattered to each
-    photon's segment.
+    exceed it); dL/dp = (2/N) sum_i sum_k J_ik^T (uv_i - target_i), scattered
+    to the k-th parametrised segment on photon i's path (the chain rule over
+    every segment the path meets).
     """
     use = mask.astype(bool) & np.isin(res["fate"], [DETECTED, QE_REJECTED])
     if residual_cut is not None:
         with np.errstate(invalid="ignore"):
             use &= np.linalg.norm(res["hit_uv"] - targets, axis=1) <= residual_cut
-    if np.any(res["segment"][use] == -2):
-        raise ValueError("a masked photon hits two parametrised segments; its Jacobian is not tracked")
+    if np.any(res["segment"][use] == -3):
+        raise ValueError(f"a masked photon meets more than {MAX_PATH_SEGS} parametrised segments")
     nuse = int(use.sum())
     grad = np.zeros((n_seg, 6))
     if nuse == 0:
         return 0.0, grad, 0
     r = res["hit_uv"][use] - targets[use]
     loss = float((r * r).sum() / nuse)
-    seg = res["segment"][use]
-    has = seg >= 0
-    contrib = np.einsum("nk,nkp->np", r[has], res["jac"][use][has]) * (2.0 / nuse)
-    np.add.at(grad, seg[has], contrib)
+    segs = res["segments"][use]
+    jacs = res["jacs"][use]
+    for k in range(MAX_PATH_SEGS):
+        has = segs[:, k] >= 0
+        contrib = np.einsum("nk,nkp->np", r[has], jacs[has, k]) * (2.0 / nuse)
+        np.add.at(grad, segs[has, k], contrib)
     return loss, grad, nuse
 
 

@@ -817,23 +817,12 @@ typedef struct {
     uint64_t begin, end;
 } job;
 
-static void jacobian(const orc_scene *s, const photon *ph, const pathrec *path, int npath, int32_t *seg_out,
-                     double *J)
+/* Forward-mode pass along the recorded path with tangents on the six
+ * parameters of segment `tracked` only (every other segment held at its
+ * current parameters): J = d(u,v)/d(params of tracked), [2][6]. */
+static void jacobian_of(const orc_scene *s, const photon *ph, const pathrec *path, int npath, int tracked, double *J)
 {
-    /* first parametrised segment on the path */
-    int tracked = -1;
     int64_t nc = s->d.n_cap, nr = s->d.n_rect, tb = nc + nr + 2;
-    for (int q = 0; q < npath; ++q) {
-        int64_t p = path[q].prim;
-        int k = -1;
-        if (p < nc) k = s->cap_seg[p];
-        else if (p >= tb) k = s->tri_seg[p - tb];
-        if (k >= 0) {
-            if (tracked < 0) tracked = k;
-            else if (k != tracked) { *seg_out = -2; for (int m = 0; m < 12; ++m) J[m] = NAN; return; }
-        }
-    }
-    *seg_out = tracked;
     dv o = dvc(ph->o), d = dvc(ph->d);
     for (int q = 0; q < npath; ++q) {
         int64_t p = path[q].prim;
@@ -891,6 +880,47 @@ static void jacobian(const orc_scene *s, const photon *ph, const pathrec *path, 
         }
     }
     for (int m = 0; m < 12; ++m) J[m] = NAN;
+}
+
+/* Jacobians of the detector coordinates with respect to every parametrised
+ * segment on the path: one forward-mode pass per distinct segment (the total
+ * derivative is their sum by the chain rule).  segs[k] / Js[k] for the k-th
+ * distinct segment met; the single-segment outputs seg_out / J keep the one
+ * segment (-1 none; -2 several, -3 more than ORC_MAX_PATH_SEGS: J NaN). */
+static void jacobian(const orc_scene *s, const photon *ph, const pathrec *path, int npath, int32_t *seg_out,
+                     double *J, int32_t *segs, double *Js)
+{
+    int64_t nc = s->d.n_cap, nr = s->d.n_rect, tb = nc + nr + 2;
+    int found[ORC_MAX_PATH_SEGS], nfound = 0, too_many = 0;
+    for (int q = 0; q < npath; ++q) {
+        int64_t p = path[q].prim;
+        int k = -1;
+        if (p < nc) k = s->cap_seg[p];
+        else if (p >= tb) k = s->tri_seg[p - tb];
+        if (k < 0) continue;
+        int seen = 0;
+        for (int m = 0; m < nfound; ++m) seen |= found[m] == k;
+        if (seen) continue;
+        if (nfound == ORC_MAX_PATH_SEGS) { too_many = 1; break; }
+        found[nfound++] = k;
+    }
+    for (int m = 0; m < ORC_MAX_PATH_SEGS; ++m) segs[m] = -1;
+    for (int m = 0; m < 12 * ORC_MAX_PATH_SEGS; ++m) Js[m] = NAN;
+    for (int m = 0; m < 12; ++m) J[m] = NAN;
+    if (too_many) { *seg_out = -3; return; }
+    for (int m = 0; m < nfound; ++m) {
+        segs[m] = found[m];
+        jacobian_of(s, ph, path, npath, found[m], Js + 12 * m);
+    }
+    if (nfound == 0) {
+        *seg_out = -1;
+        jacobian_of(s, ph, path, npath, -1, J);   /* no tangent: zeros */
+    } else if (nfound == 1) {
+        *seg_out = found[0];
+        memcpy(J, Js, 12 * sizeof(double));
+    } else {
+        *seg_out = -2;
+    }
 }
 
 static void trace_photon(const job *jb, uint64_t i)
@@ -1008,16 +1038,21 @@ static void trace_photon(const job *jb, uint64_t i)
     if (out->roulette_margin) out->roulette_margin[i] = rmargin;
     if (out->pixel_margin) out->pixel_margin[i] = pmargin;
     if (out->n_bounce) out->n_bounce[i] = nb;
-    if (jb->with_jac && (out->jac || out->segment)) {
-        int32_t sg = -1;
-        double J[12];
+    if (jb->with_jac && (out->jac || out->segment || out->segments || out->jacs)) {
+        int32_t sg = -1, sgs[ORC_MAX_PATH_SEGS];
+        double J[12], Js[12 * ORC_MAX_PATH_SEGS];
         if (fate == ORC_DETECTED || fate == ORC_QE_REJECTED) {
-            jacobian(s, &ph, path, npath, &sg, J);
+            jacobian(s, &ph, path, npath, &sg, J, sgs, Js);
         } else {
             for (int m = 0; m < 12; ++m) J[m] = NAN;
+            for (int m = 0; m < ORC_MAX_PATH_SEGS; ++m) sgs[m] = -1;
+            for (int m = 0; m < 12 * ORC_MAX_PATH_SEGS; ++m) Js[m] = NAN;
         }
         if (out->segment) out->segment[i] = sg;
         if (out->jac) for (int m = 0; m < 12; ++m) out->jac[12 * i + m] = J[m];
+        if (out->segments) for (int m = 0; m < ORC_MAX_PATH_SEGS; ++m) out->segments[ORC_MAX_PATH_SEGS * i + m] = sgs[m];
+        if (out->jacs)
+            for (int m = 0; m < 12 * ORC_MAX_PATH_SEGS; ++m) out->jacs[12 * ORC_MAX_PATH_SEGS * i + m] = Js[m];
     }
 }
 

@@ -31,6 +31,7 @@ extern "C" {
 #endif
 
 #define ORC_MAX_TABLE 32
+#define ORC_MAX_PATH_SEGS 4   /* distinct parametrised segments whose Jacobians one path reports */
 
 enum { ORC_DETECTED = 0, ORC_QE_REJECTED = 1, ORC_ABSORBED_MIRROR = 2,
        ORC_ABSORBED = 3, ORC_ESCAPED = 4, ORC_MAX_BOUNCES = 5, ORC_PREFILTERED = 6 };
@@ -106,9 +107,16 @@ typedef struct {
     double *pixel_margin;      /* distance (mm) of the detector hit to the nearest pixel boundary */
     double *roulette_margin;   /* smallest |u - p| over roulette decisions on the path */
     int32_t *n_bounce;         /* surfaces hit */
-    int32_t *segment;          /* parametrised segment hit (-1 none, -2 more than one) */
-    double *jac;               /* [n][2][6] d(u,v)/d(segment params), NaN when undefined */
+    int32_t *segment;          /* parametrised segment hit (-1 none, -2 more than one, -3 more than ORC_MAX_PATH_SEGS) */
+    double *jac;               /* [n][2][6] d(u,v)/d(segment params), NaN when undefined (also for -2 and -3) */
     double *hit_time;          /* [n] ns from the track origin to the detector hit, NaN unless DETECTED / QE_REJECTED */
+    /* Every parametrised segment on the path, in the order first met, and the
+     * Jacobian of (u,v) with respect to each one's six parameters, all other
+     * segments held fixed; the total derivative of (u,v) is the sum over k of
+     * jacs[i][k] applied to segments[i][k]'s parameter change.  Unused slots:
+     * segment -1, Jacobian NaN.  Set only for DETECTED / QE_REJECTED. */
+    int32_t *segments;         /* [n][ORC_MAX_PATH_SEGS] */
+    double *jacs;              /* [n][ORC_MAX_PATH_SEGS][2][6] */
 } orc_outputs;
 
 /* Cherenkov photons per mm of track (Frank-Tamm): 2 pi alpha times the

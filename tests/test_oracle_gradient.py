@@ -49,8 +49,8 @@ def test_dual_jacobian_matches_central_differences_analytic(orc, perturbed):
     res = orc.propagate(orc.Scene(scene, params=params), src, n, seed, jacobian=True)
     on = np.isin(res["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (res["edge_margin"] > 1.0) & (res["segment"] >= 0)
     assert on.sum() > 300
-    # with a 600 mm detector only the four central segments send light onto it
-    assert len(np.unique(res["segment"][on])) >= 4
+    # the enlarged flat mirror and detector image every one of the 16 segments
+    assert len(np.unique(res["segment"][on])) == 16
     seg = np.where(on, res["segment"], -1)
     Jfd = _fd_jacobian(orc, scene, src, n, seed, params, seg)
     Jd = res["jac"][on]
@@ -138,3 +138,54 @@ def test_meshed_segment_jacobian_matches_central_differences(orc):
     scale = np.abs(Jd).max(axis=(0, 1))
     err = np.abs(Jd - Jf).max(axis=(0, 1)) / scale
     assert np.all(err < 1e-4), err
+
+
+def test_jacobian_over_two_segments_matches_central_differences(orc):
+    """Paths that reflect off two parametrised segments (a spherical cap, then the flat mirror
+    as a moving mesh): the oracle's per-segment duals against central differences of its own
+    hits, column by column, and the chain rule's sum over both segments against a central
+    difference along a random direction in all 102 parameters."""
+    scene = I.scene_g4_moving_flat()
+    rng = np.random.default_rng(1006)
+    src = I.batch_source(I.sample_tracks(rng, 80), np.full(80, 60))
+    n = 4800
+    seed = I.SEED_BASE + 4
+    params = I.perturbed_params(4, scene)
+    res = orc.propagate(orc.Scene(scene, params=params), src, n, seed, jacobian=True)
+    on = np.isin(res["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (res["edge_margin"] > 1.0)
+    segs = res["segments"]
+    assert np.all(res["segment"][on] == -2) and np.all(segs[on, 1] == 16) and np.all(segs[on, 2] == -1)
+    assert np.all(np.isnan(res["jac"][on]))
+    assert on.sum() > 300 and len(np.unique(segs[on, 0])) >= 12
+    assert np.all(np.isnan(res["jacs"][on, 2:]))
+    # scaling the flat about its centre moves hits by ~1e-6 mm per mm of "radius": 1 mm steps
+    Hf = np.array([1e-6, 1e-6, 1.0, 1e-3, 1e-3, 1e-3])
+    for slot, tol in ((0, 1e-5), (1, 1e-4)):
+        seg = np.where(on, segs[:, slot], -1)
+        Jfd = _fd_jacobian(orc, scene, src, n, seed, params, seg, H=H if slot == 0 else Hf)
+        Jd = res["jacs"][on, slot]
+        cols = [0, 1, 2, 3, 4, 5]
+        if slot == 1:
+            # scaling a plane about a point on it leaves the plane in place: dX/dR = 0
+            assert np.abs(Jd[:, :, 2]).max() < 1e-12 and np.abs(Jfd[on][:, :, 2]).max() < 1e-8
+            cols = [0, 1, 3, 4, 5]
+        scale = np.abs(Jd[:, :, cols]).max(axis=(0, 1))
+        err = np.abs(Jd[:, :, cols] - Jfd[on][:, :, cols]).max(axis=(0, 1)) / scale
+        assert np.all(err < tol), (slot, err)
+    # total derivative: sum of both segments' Jacobians along one direction of all parameters
+    step = rng.normal(size=params.shape) * H
+    rp = orc.propagate(orc.Scene(scene, params=params + step), src, n, seed)
+    rm = orc.propagate(orc.Scene(scene, params=params - step), src, n, seed)
+    fd = (rp["hit_uv"] - rm["hit_uv"])[on] / 2.0
+    lin = np.zeros_like(fd)
+    for slot in range(2):
+        lin += np.einsum("npk,nk->np", res["jacs"][on, slot], step[segs[on, slot]])
+    assert np.abs(fd - lin).max() <= 1e-5 * np.abs(lin).max()
+    # the loss gradient takes both segments' contributions
+    target = orc.propagate(orc.Scene(scene, params=scene["params"]), src, n, seed)
+    mask = on & np.isin(target["fate"], [orc.DETECTED, orc.QE_REJECTED]) & (target["edge_margin"] > 1.0)
+    loss, grad, nuse = orc.mse_loss_and_grad(res, target["hit_uv"], mask, 17)
+    assert nuse == mask.sum() > 300 and np.all(grad[16] != 0.0)
+    r = res["hit_uv"][mask] - target["hit_uv"][mask]
+    want16 = 2.0 / nuse * np.einsum("np,npk->k", r, res["jacs"][mask, 1])
+    assert np.allclose(grad[16], want16, rtol=1e-12, atol=0)
