@@ -245,11 +245,27 @@ def _empty_rects():
             "axis_u": np.zeros((0, 3)), "axis_v": np.zeros((0, 3)), "half": np.zeros((0, 2))}
 
 
-def _flat_rect():
+def _flat_rect(half_u=0.5 * FLAT_SIZE, v_range=(-0.5 * FLAT_SIZE, 0.5 * FLAT_SIZE)):
+    """The flat mirror in G1's flat plane: |u| <= half_u, v in v_range about G1's flat centre."""
     c, n, u, v, _ = flat_frame()
-    h = 0.5 * FLAT_SIZE
-    return {"material": np.array([MIRROR], np.int32), "center": c[None], "normal": n[None],
-            "axis_u": u[None], "axis_v": v[None], "half": np.array([[h, h]])}
+    cc = c + 0.5 * (v_range[0] + v_range[1]) * v
+    hv = 0.5 * (v_range[1] - v_range[0])
+    return {"material": np.array([MIRROR], np.int32), "center": cc[None], "normal": n[None],
+            "axis_u": u[None], "axis_v": v[None], "half": np.array([[half_u, hv]])}
+
+
+# G4's flat mirror and detector.  G1's 600 x 600 mm flat mirror intercepts the
+# reflected light of the four central cells of a 4 x 4 split only: the beams
+# of the outer cells land beyond its edges (the bottom row's below the lower
+# edge, which cannot move down without shadowing the forward beam).  G4 keeps
+# G1's flat plane but extends the mirror to 1400 mm along u and from 500 mm
+# below to 800 mm above G1's flat centre along v, with the large scene's
+# 512 x 512-pixel detector, so that every segment sends light to the detector.
+# The lower edge then shadows the part of the forward cone above ~0.19 rad
+# upward; those photons meet the flat mirror's back face and are absorbed.
+G4_FLAT_HALF_U = 700.0
+G4_FLAT_V = (-500.0, 800.0)
+G4_DET_PIXELS = 512
 
 
 def _caps_for_cells(cells, segment_ids):
@@ -326,13 +342,46 @@ def scene_g2(sphere_quads=(346, 289), box_quads=29):
 
 
 def scene_g4():
-    """G1 with the sphere split into 4 columns x 4 rows of analytic segments (300 x 250 mm)."""
+    """G1's sphere split into 4 columns x 4 rows of analytic segments (300 x 250 mm), with the
+    enlarged flat mirror and the 512 x 512-pixel detector that image every segment."""
     cells = grid_cells(4, 4)
     s = scene_g1()
     s["name"] = "G4-segmented"
     s["segments"] = _segments_for_cells(cells)
     s["params"] = _nominal_params(len(cells))
     s["caps"] = _caps_for_cells(cells, list(range(len(cells))))
+    s["rects"] = _flat_rect(G4_FLAT_HALF_U, G4_FLAT_V)
+    s["detector"] = _detector(G4_DET_PIXELS)
+    return s
+
+
+# The flat mirror of scene_g4_moving_flat as a segment: pivot at its centre,
+# axis along its normal, tilt axes along its u and v; "radius" R scales the
+# mirror about its centre by R / FLAT_R0.
+FLAT_R0 = 2000.0
+
+
+def scene_g4_moving_flat():
+    """G4 with its flat mirror turned into a parametrised mesh (segment 16, two triangles).
+
+    Every detected photon reflects off one spherical cap and then the flat, so
+    its hit depends on two segments' parameters.
+    """
+    s = scene_g4()
+    s["name"] = "G4-moving-flat"
+    r = s["rects"]
+    c, n, u, v = r["center"][0], r["normal"][0], r["axis_u"][0], r["axis_v"][0]
+    hu, hv = r["half"][0]
+    seg = s["segments"]
+    s["segments"] = {"pivot": np.vstack([seg["pivot"], c]), "u0": np.vstack([seg["u0"], n]),
+                     "e1": np.vstack([seg["e1"], u]), "e2": np.vstack([seg["e2"], v]),
+                     "radius0": np.append(seg["radius0"], FLAT_R0)}
+    p = np.zeros((17, 6))
+    p[:16] = s["params"]
+    p[16, 2] = FLAT_R0
+    s["params"] = p
+    s["rects"] = _empty_rects()
+    s["meshes"] = [{"vertices": rect_mesh(c, n, u, v, hu, hv, 1, 1), "material": MIRROR, "segment": 16}]
     return s
 
 

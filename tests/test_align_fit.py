@@ -45,16 +45,34 @@ def _lit(orc, tgt, on, nseg, min_photons):
 
 
 def test_adam_fit_recovers_analytic_misalignment(orc):
-    """G4 analytic caps: tilts and radius of every imaged segment."""
+    """G4 analytic caps: tilts and radius of all 16 segments (every one is imaged), 600 steps."""
     scene = I.scene_g4()
-    src, n, seed, tp, tgt, on = _problem(orc, 4, scene, 1000, 10)
-    p, losses, p0 = _oracle_fit(orc, scene, src, n, seed, tgt, on)
-    lit = _lit(orc, tgt, on, len(p), 50)
-    assert lit.sum() >= 4
+    src, n, seed, tp, tgt, on = _problem(orc, 4, scene, 2000, 10)
+    p, losses, p0 = _oracle_fit(orc, scene, src, n, seed, tgt, on, steps=600)
+    assert _lit(orc, tgt, on, len(p), 20).sum() == 16
     assert losses[-1] < 1e-8 * losses[0]
-    assert np.abs(p[lit, :2] - tp[lit, :2]).max() < 1e-8          # rad (sigma 5e-4)
-    assert np.abs(p[lit, 2] - tp[lit, 2]).max() < 1e-2           # mm (sigma 5)
-    assert np.array_equal(p[~lit], p0[~lit])                      # unseen segments do not move
+    # the bottom corner cells send ~40 photons each over a narrow range of
+    # angles, so their radius and tilts converge more slowly
+    assert np.abs(p[:, :2] - tp[:, :2]).max() < 1e-6             # rad (sigma 5e-4)
+    assert np.abs(p[:, 2] - tp[:, 2]).max() < 0.5                # mm (sigma 5)
+    well = _lit(orc, tgt, on, len(p), 60)
+    assert well.sum() >= 12
+    assert np.abs(p[well, :2] - tp[well, :2]).max() < 1e-8
+    assert np.abs(p[well, 2] - tp[well, 2]).max() < 1e-2
+    assert np.array_equal(p[:, 3:], p0[:, 3:])                    # pivot shifts are not fitted
+
+
+def test_adam_fit_leaves_unseen_segments_in_place(orc):
+    """G1's 600 mm flat mirror and 208-pixel detector image only the four central cells of the
+    4 x 4 split: the other twelve get no photon, hence a zero gradient, and must not move."""
+    scene = I.scene_g4()
+    g1 = I.scene_g1()
+    scene["rects"], scene["detector"] = g1["rects"], g1["detector"]
+    src, n, seed, tp, tgt, on = _problem(orc, 4, scene, 500, 10)
+    p, losses, p0 = _oracle_fit(orc, scene, src, n, seed, tgt, on, steps=100)
+    seen = _lit(orc, tgt, on, len(p), 1)
+    assert seen.sum() == 4 and losses[-1] < 1e-2 * losses[0]
+    assert np.array_equal(p[~seen], p0[~seen])
 
 
 def test_adam_fit_with_residual_cut_recovers_meshed_tilts(orc):
