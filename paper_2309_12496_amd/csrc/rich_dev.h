@@ -28,6 +28,10 @@ constexpr uint32_t kLeafBit = 0x80000000u;     // leaf or instance
 constexpr uint32_t kInstBit = 0x40000000u;     // with kLeafBit: instance reference
 constexpr uint32_t kExitMarker = 0xFFFFFFFEu;  // stack entry: return to the world frame
 constexpr uint32_t kLeafMaxTris = 8;
+// Scene size limits: traversal addresses triangles (64 B) and nodes (128 B)
+// with 32-bit byte offsets from the array bases.
+constexpr int64_t kMaxTriangles = int64_t(1) << 26;   // exclusive
+constexpr int64_t kMaxNodes = int64_t(1) << 25;       // exclusive
 // leaf: kLeafBit | (count-1) << 27 | first   (first < 2^27, count 1..8)
 // instance: kLeafBit | kInstBit | index
 __host__ __device__ inline uint32_t make_leaf(uint32_t first, uint32_t count) {

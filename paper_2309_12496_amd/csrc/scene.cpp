@@ -90,17 +90,23 @@ rich_status validate(const rich_scene_desc *d) {
             return set_error(RICH_EINVAL, "rect %d: bad frame or size", i);
     }
     if (d->n_meshes < 0 || (d->n_meshes > 0 && !d->meshes)) return set_error(RICH_EINVAL, "bad meshes");
+    // Sizes first, before any vertex is read.  Traversal forms triangle and
+    // node byte offsets in 32 bits (64-byte triangles, 128-byte nodes), so a
+    // scene holds fewer than 2^26 triangles and 2^25 BVH nodes.
     int64_t total = 0;
     for (int i = 0; i < d->n_meshes; ++i) {
         const rich_mesh &m = d->meshes[i];
         if (m.n_tri < 0 || (m.n_tri > 0 && !m.vertices)) return set_error(RICH_EINVAL, "mesh %d: bad triangle array", i);
         if (m.material < 0 || m.material >= d->n_materials) return set_error(RICH_EINVAL, "mesh %d: bad material", i);
         if (m.segment < -1 || m.segment >= d->n_segments) return set_error(RICH_EINVAL, "mesh %d: segment out of range", i);
+        total += m.n_tri;
+        if (total >= kMaxTriangles) return set_error(RICH_EINVAL, "too many triangles (limit 2^26 - 1)");
+    }
+    for (int i = 0; i < d->n_meshes; ++i) {
+        const rich_mesh &m = d->meshes[i];
         for (int64_t q = 0; q < 9 * m.n_tri; ++q)
             if (!std::isfinite(m.vertices[q])) return set_error(RICH_EINVAL, "mesh %d: non-finite vertex", i);
-        total += m.n_tri;
     }
-    if (total >= (int64_t)1 << 27) return set_error(RICH_EINVAL, "too many triangles (limit 2^27)");
     const rich_detector &t = d->detector;
     if (!finite3(t.center) || !unit3(t.normal) || !unit3(t.axis_u) || !unit3(t.axis_v) || !(t.half[0] > 0) ||
         !(t.half[1] > 0) || !(t.pitch > 0) || t.nx <= 0 || t.ny <= 0)
@@ -380,6 +386,12 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
             cs.B[a] = c.axis_b[a];
         }
         for (int a = 0; a < 4; ++a) cs.bounds[a] = c.bounds[a];
+    }
+
+    if (nodes.size() >= (size_t)kMaxNodes) {
+        free_scene(s);
+        (void)hipSetDevice(prev);
+        return set_error(RICH_EINVAL, "BVH of %zu nodes (limit 2^25 - 1)", nodes.size());
     }
 
     // --- upload

@@ -125,3 +125,20 @@ def test_header_is_plain_c_and_links(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, (r.returncode, r.stderr)
     assert r.stdout.startswith("0.4270421")
+
+
+@pytest.mark.parametrize("counts", [(1 << 26,), (1 << 25, 1 << 25), (3, (1 << 26) - 2)])
+def test_scene_triangle_limit_is_refused_before_vertices_are_read(lib, counts):
+    """Traversal forms 32-bit byte offsets of 64-byte triangles and 128-byte nodes, so a scene
+    holds at most 2^26 - 1 triangles.  The count is checked before any vertex is read: here the
+    meshes claim more triangles than their arrays hold, and the build must refuse them."""
+    from paper_2309_12496_amd import rich as R
+    sc = I.scene_g2(sphere_quads=(4, 4))
+    desc, keep = R.scene_desc(sc)
+    assert desc.n_meshes >= len(counts)
+    for k, c in enumerate(counts):
+        desc.meshes[k].n_tri = c
+    out = C.c_void_p()
+    assert R._L.rich_build_scene(C.byref(desc), 0, C.byref(out)) == R.RICH_EINVAL
+    assert not out.value
+    assert "too many triangles" in R.rich_last_error()
