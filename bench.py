@@ -150,10 +150,12 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
     a_ms = time_steps(lambda: R.rich_propagate_adjoint(sc.handle, None, b, n, cfg["seed"], 0, None, targets, mask,
                                                        None, grad, loss, stream), steps, 1, stream)
     assert sc.status() == 0
+    n_mask = int(mask.sum())
     return {"workload": cfg["name"], "photons_per_step": n, "parameters": 6 * sc.n_segments,
             "forward_ms": s_ms, "adjoint_ms": a_ms, "ms_per_step": s_ms + a_ms,
             "photons_per_s": n / ((s_ms + a_ms) * 1e-3), "forward_photons_per_s": n / (s_ms * 1e-3),
-            "loss_mm2": float(loss), "masked_photons": int(mask.sum()), "scene_build_s": round(build_s, 3),
+            "loss_mm2": float(loss), "masked_photons": n_mask,
+            "adjoint_masked_photons_per_s": n_mask / (a_ms * 1e-3), "scene_build_s": round(build_s, 3),
             "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu}}
 
 
@@ -187,9 +189,11 @@ def form_align_fit(R, I, stream, steps):
     p0 = np.asarray(cfg["scene"]["params"], np.float32).astype(np.float64)
     tp = np.asarray(cfg["target_params"], np.float64)
     moved = np.any(p != p0, axis=1)
-    n = cfg["n_photons"]
+    # a step retraces only the photons of the mask (those the target run detected)
+    traced = int(on.sum())
     return {"workload": cfg["name"] + ", Adam fit of tilts and radii from the nominal geometry",
-            "photons_per_step": n, "steps": steps, "ms_per_step": ms, "photons_per_s": n / (ms * 1e-3),
+            "emitted_photons": cfg["n_photons"], "traced_photons_per_step": traced, "steps": steps,
+            "ms_per_step": ms, "traced_photons_per_s": traced / (ms * 1e-3),
             "loss_first_mm2": float(losses[0]), "loss_last_mm2": float(losses[-1]),
             "segments_fitted": int(moved.sum()),
             "max_tilt_error_rad": float(np.abs(p[moved, :2] - tp[moved, :2]).max()),

@@ -288,27 +288,63 @@ typedef struct rich_tuning {
 
 /* ----------------------------------------------------------------- calls ---- */
 
-/* Build a scene on `device` from host FP64 data: validates, builds SAH BVH4s
- * (one per mesh instance, in that instance's local frame, with facet normals
- * computed in FP64) and a top-level BVH4, and uploads FP32 copies.
- * Synchronous.  *out is NULL on failure. */
+/* Build a scene on `device` from host FP64 data (paper Section 4.1: the
+ * detector reduced to mirrors, absorbing walls and the photodetector plane,
+ * meshed surfaces given as triangles): validates, builds SAH BVH4s (one per
+ * mesh instance, in that instance's local frame, with facet normals computed
+ * in FP64) and a top-level BVH4, and uploads FP32 copies.  The desc arrays
+ * are read during the call only; the scene owns its device memory until
+ * rich_destroy_scene.  Synchronous.  *out is NULL on failure.
+ * Errors: RICH_EINVAL for a NULL pointer, a bad table, an unknown material,
+ * a non-finite or non-unit frame, an empty cell or rectangle, a segment or
+ * material index out of range, 2^26 or more triangles, or a BVH of 2^25 or
+ * more nodes, or a device that does not exist; RICH_ENOMEM / RICH_EDEVICE when host or
+ * device memory cannot be had. */
 rich_status rich_build_scene(const rich_scene_desc *desc, int device, rich_scene **out);
+
+/* Free the scene and everything it holds on the device.  The caller makes
+ * sure no launch on the scene is still running.  RICH_EINVAL for NULL. */
 rich_status rich_destroy_scene(rich_scene *s);
+
+/* Copy the scene's statistics into *out (host).  RICH_EINVAL for NULL. */
 rich_status rich_scene_info(const rich_scene *s, rich_scene_stats *out);
 
-/* Replace the segment parameters from a device array [n_segments][6] (FP32)
- * and refresh the derived cap and instance data on the stream. */
+/* Mirror-segment alignment (an extension beyond the paper, which keeps its
+ * mirrors fixed): replace the segment parameters from a device array
+ * [n_segments][6] (FP32, the caller's, read on the stream) and refresh the
+ * derived cap centres, instance transforms and top-level BVH boxes on the
+ * stream.  Meshed segments move as instances, so no triangle is rebuilt and
+ * no parameter range is refused.  Errors: RICH_EINVAL (NULL pointers),
+ * RICH_ESTATE (the scene has no segments), RICH_EDEVICE (launch failed). */
 rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipStream_t stream);
 
 /* Propagate photons first_photon_id .. first_photon_id + n_photons - 1 of a
- * single source, seeded by `seed` (Philox4x32-10, counter = photon id). */
+ * single source, seeded by `seed` (Philox4x32-10, counter = photon id):
+ * generation on the Cherenkov cone (Section 3) or the given arrays (Section
+ * 4.2), straight flight to the closest surface, specular reflection with the
+ * reflectivity roulette and the QE roulette at the detector (Section 4.3, at
+ * the surface as Section 7 proposes), and the detector hit as global point,
+ * (u, v) and pixel (Section 4.4); the compact hit list is Section 7's list of
+ * global hits.  Every output array is the caller's device memory, indexed by
+ * g - first_photon_id; NULL skips it.  Asynchronous on `stream`.
+ * Errors (synchronous, nothing launched): RICH_EINVAL for NULL scene or
+ * source, an unknown source kind, n beta <= 1, a bad table or prefilter
+ * material, a hit list without its counter; RICH_ERANGE when the id range
+ * wraps 2^64 or n_photons > 2^40; RICH_EDEVICE when the launch fails.
+ * Traversal-stack and hit-list overflow raise device flags
+ * (rich_get_status). */
 rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,
                            uint64_t first_photon_id, const rich_outputs *out, hipStream_t stream);
 
-/* Propagate every photon of a batch (n_photons = offsets[n_tracks], else
- * the device raises RICH_FLAG_BATCH_SIZE; ids n_photons.. are then left out,
- * or photons beyond the last track's count are drawn from it) in one
- * persistent launch replayed from a captured HIP graph.  tune = NULL picks the
+/* The computation of rich_propagate for many tracks in one launch (an
+ * extension: the paper instantiates one emitter for all the photons it is
+ * handed, Section 4.2).  Propagate every photon of a batch (n_photons =
+ * offsets[n_tracks], else the device raises RICH_FLAG_BATCH_SIZE; ids
+ * n_photons.. are then left out, or photons beyond the last track's count
+ * are drawn from it) in one persistent launch replayed from a captured HIP
+ * graph.  Outputs are indexed by the global id g.  Errors as rich_propagate,
+ * plus RICH_EINVAL for a bad tuning and RICH_ENOMEM when autotuning or graph
+ * capture fails.  tune = NULL picks the
  * launch shape with the autotuner (cached per scene and in the JSON file named
  * by RICH_TUNE_CACHE, if set; tuning synchronises the stream).  The call
  * captures and launches its own graph, so it is not itself meant to be
@@ -323,7 +359,9 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
 rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
                           rich_tuning *out);
 
-/* Reverse-mode derivative of detector hit coordinates (u, v) with respect to
+/* Reverse-mode derivative (an extension beyond the paper, which does not
+ * differentiate; the DrJit engine its Section 2 builds on is a compiler for
+ * differentiable rendering) of detector hit coordinates (u, v) with respect to
  * the segment parameters, at the scene's current parameters, for the photons
  * of either `src` (ids first_photon_id..) or `batch` (ids 0..), exactly one
  * non-NULL.  Interior derivative: visibility changes at edges are ignored.
@@ -341,7 +379,13 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
  * no photon counts, n_photons = 0 included).  The sums are deterministic
  * (fixed reduction order).  The first call, and a call with more photons than
  * any before, allocates the scene's partial-sum buffer: a caller that
- * captures this call in a graph makes one such call first. */
+ * captures this call in a graph makes one such call first.
+ * Errors: RICH_EINVAL (both or neither of src/batch or of
+ * dev_grad_uv/dev_targets, a cut without targets, NULL dev_grad_params, a
+ * batch not starting at id 0), RICH_ESTATE (no segments), RICH_ERANGE (id
+ * range), RICH_ENOMEM (partial sums), RICH_EDEVICE (launch).  A path that
+ * meets more surfaces than the adjoint records raises
+ * RICH_FLAG_PATH_OVERFLOW and is left out. */
 rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
                                    uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
@@ -416,7 +460,8 @@ typedef struct rich_film {
 rich_status rich_film_readout(const rich_film *film, const uint8_t *dev_fate, const float *dev_hit_uv,
                               uint64_t n_photons, float *dev_image, uint8_t *dev_hits, hipStream_t stream);
 
-/* Cherenkov photons emitted per mm of track at velocity beta (Frank-Tamm):
+/* Cherenkov photons emitted per mm of track at velocity beta (Frank-Tamm,
+ * the step before the paper's Section 3 cone, which Geant4 supplies there):
  * 2 pi alpha times the integral over [lambda_min, lambda_max] of
  * (1 - 1/(beta n(lambda))^2)^+ / lambda^2, lambda in mm, alpha the fine
  * structure constant; n from `dispersion` (NULL or 0 nodes: n_radiator).
@@ -426,7 +471,9 @@ rich_status rich_cherenkov_yield(const rich_dispersion *dispersion, double n_rad
                                  double lambda_min, double lambda_max, double *photons_per_mm);
 
 /* Synchronise the stream, return the device flags raised since the last call
- * (RICH_FLAG_*) and clear them.  Returns RICH_EOVERFLOW when any is set. */
+ * (RICH_FLAG_*) in *flags (host; NULL: not returned) and clear them.  Returns
+ * RICH_EOVERFLOW when any is set, RICH_EDEVICE when the stream reports an
+ * error (a fault of an earlier launch surfaces here). */
 rich_status rich_get_status(rich_scene *s, hipStream_t stream, uint32_t *flags);
 
 /* Thread-local description of the last error ("" if none). */
