@@ -392,6 +392,26 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
                                    const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
                                    hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or fitting loops, harnesses that forbid hipMalloc):
+ * rich_propagate_adjoint with the same arguments, results and errors, except
+ * that its block partial sums live in a static device array that the library
+ * holds on every device it runs on (8 MiB, 2^21 floats, kept until the
+ * process ends) instead of the scene's buffer, so it never calls hipMalloc
+ * or hipFree.  The partial sums take B x (6 n_segments + 2) floats with
+ * B = min(ceil(n_photons / 2048), 16 x compute units); a call that needs more
+ * than 2^21 returns RICH_ERANGE before launching anything (on a 256-CU
+ * MI355X, any photon count works up to 85 segments).  Every call on one
+ * device shares that device's array: calls that overlap on one device
+ * (different streams, or different host threads) race and give wrong sums;
+ * order them on one stream.  The array needs no clearing: each launch writes
+ * every partial it later reads. */
+rich_status rich_propagate_adjoint_noalloc(rich_scene *s, const rich_source *src, const rich_batch *batch,
+                                           uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
+                                           const float *dev_grad_uv, const float *dev_targets,
+                                           const uint8_t *dev_mask, const float *dev_residual_cut,
+                                           float *dev_grad_params, float *dev_loss, hipStream_t stream);
+
 /* Optimiser of the alignment fit (extension beyond the paper, built on
  * rich_propagate_adjoint): one Adam step (Kingma and Ba, ICLR 2015) over the
  * segment parameters in normalised coordinates z = (p - p0) / scale, with

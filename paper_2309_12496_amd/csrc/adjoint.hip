@@ -20,10 +20,17 @@
 // the blocks in order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.h"
 #include "trace.h"
 
 namespace rich {
+
+// Block partial sums of rich_propagate_adjoint_noalloc.  In host code the
+// name stands for a host-side shadow: kernels get the device address that
+// adjoint_scratch looks up, never this name.
+__device__ __align__(256) float scratch[kAdjScratchFloats];
 
 namespace {
 
@@ -317,6 +324,21 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float *partia
 }
 
 int adjoint_block_size() { return kAdjBlock; }
+
+hipError_t adjoint_scratch(int device, float **ptr) {
+    static std::mutex mu;
+    static float *addr[kAdjScratchDevices] = {};
+    if (device < 0 || device >= kAdjScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<float *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const AdjointArgs &a, uint64_t n, uint64_t first,
                           uint64_t seed, int n_blocks, hipStream_t st) {

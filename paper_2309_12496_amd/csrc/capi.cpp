@@ -560,11 +560,13 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
     }
 }
 
-rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
-                                   uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
-                                   const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
-                                   const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
-                                   hipStream_t stream) {
+// Shared by both adjoint entry points: argument checks, source set-up, the
+// grid, and the partial-sum buffer (the scene's, grown with hipMalloc, or the
+// static per-device array when noalloc is set).
+static rich_status adjoint_call(rich_scene *s, const rich_source *src, const rich_batch *batch, uint64_t n_photons,
+                                uint64_t seed, uint64_t first_photon_id, const float *dev_grad_uv,
+                                const float *dev_targets, const uint8_t *dev_mask, const float *dev_residual_cut,
+                                float *dev_grad_params, float *dev_loss, hipStream_t stream, bool noalloc) {
     if (!s) return set_error(RICH_EINVAL, "scene is NULL");
     if ((src == nullptr) == (batch == nullptr)) return set_error(RICH_EINVAL, "give exactly one of src and batch");
     if ((dev_grad_uv == nullptr) == (dev_targets == nullptr))
@@ -586,18 +588,48 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
     uint64_t nb = (n_photons + per_block - 1) / per_block;
     int n_blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(nb, (uint64_t)s->n_cu * 16));
     size_t need = (size_t)n_blocks * (n_par + 2);
-    if (need > s->partials_floats) {
-        if (s->d_partials) (void)hipFree(s->d_partials);
-        s->d_partials = nullptr;
-        s->partials_floats = 0;
-        if (hipMalloc(&s->d_partials, need * sizeof(float)) != hipSuccess)
-            return set_error(RICH_ENOMEM, "adjoint partials allocation failed");
-        s->partials_floats = need;
+    float *partials = nullptr;
+    if (noalloc) {
+        if (need > kAdjScratchFloats)
+            return set_error(RICH_ERANGE,
+                             "no-allocation adjoint: %d blocks x %d floats of partial sums exceed its %zu floats "
+                             "(fewer segments or photons, or rich_propagate_adjoint)",
+                             n_blocks, n_par + 2, kAdjScratchFloats);
+        hipError_t e = adjoint_scratch(s->device, &partials);
+        if (e != hipSuccess)
+            return set_error(RICH_EDEVICE, "adjoint scratch address: %s", hipGetErrorString(e));
+    } else {
+        if (need > s->partials_floats) {
+            if (s->d_partials) (void)hipFree(s->d_partials);
+            s->d_partials = nullptr;
+            s->partials_floats = 0;
+            if (hipMalloc(&s->d_partials, need * sizeof(float)) != hipSuccess)
+                return set_error(RICH_ENOMEM, "adjoint partials allocation failed");
+            s->partials_floats = need;
+        }
+        partials = s->d_partials;
     }
-    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, s->d_partials, dev_grad_params, dev_loss,
-                  n_par};
+    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, partials, dev_grad_params, dev_loss, n_par};
     RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, n_blocks, stream));
     return RICH_OK;
+}
+
+rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const rich_batch *batch,
+                                   uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
+                                   const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
+                                   const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
+                                   hipStream_t stream) {
+    return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
+                        dev_residual_cut, dev_grad_params, dev_loss, stream, false);
+}
+
+rich_status rich_propagate_adjoint_noalloc(rich_scene *s, const rich_source *src, const rich_batch *batch,
+                                           uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
+                                           const float *dev_grad_uv, const float *dev_targets,
+                                           const uint8_t *dev_mask, const float *dev_residual_cut,
+                                           float *dev_grad_params, float *dev_loss, hipStream_t stream) {
+    return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
+                        dev_residual_cut, dev_grad_params, dev_loss, stream, true);
 }
 
 // Gauss-Legendre rule on [-1, 1]: nodes are the roots of P_n, found by Newton

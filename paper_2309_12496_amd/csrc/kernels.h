@@ -46,6 +46,13 @@ struct AdjointArgs {
 hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const AdjointArgs &a, uint64_t n, uint64_t first,
                           uint64_t seed, int n_blocks, hipStream_t st);
 int adjoint_block_size();
+// Partial-sum buffer of the no-allocation adjoint entry point: a file-scope
+// device array of kAdjScratchFloats floats (8 MiB) on every device the library
+// runs on.  adjoint_scratch returns its device address on `device`, which
+// must be current; the address is looked up once per device and cached.
+constexpr size_t kAdjScratchFloats = size_t(1) << 21;
+constexpr int kAdjScratchDevices = 64;
+hipError_t adjoint_scratch(int device, float **ptr);
 
 // Film read-out emulation: film coordinates x = cx + scale u, y = cy + scale v.
 struct FilmArgs {

@@ -175,6 +175,14 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     (void)hipGetDevice(&prev);
     if (hipSetDevice(device) != hipSuccess) return set_error(RICH_EDEVICE, "hipSetDevice(%d) failed", device);
 
+    // the no-allocation adjoint's partial-sum array: its address on this
+    // device, looked up once while the device is current
+    float *scratch_addr = nullptr;
+    if (adjoint_scratch(device, &scratch_addr) != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return set_error(RICH_EDEVICE, "device %d: address of the adjoint scratch array not found", device);
+    }
+
     rich_scene *s = new rich_scene();
     s->device = device;
     (void)hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, device);

@@ -142,6 +142,7 @@ _L.rich_autotune.argtypes = [C.c_void_p, C.POINTER(rich_batch), C.c_uint64, C.c_
 _L.rich_propagate_adjoint.argtypes = [C.c_void_p, C.POINTER(rich_source), C.POINTER(rich_batch), C.c_uint64,
                                       C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]
+_L.rich_propagate_adjoint_noalloc.argtypes = _L.rich_propagate_adjoint.argtypes
 _L.rich_get_status.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint32)]
 _L.rich_film_readout.argtypes = [C.POINTER(rich_film), C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                  C.c_void_p]
@@ -151,12 +152,14 @@ _L.rich_cherenkov_yield.argtypes = [C.POINTER(rich_dispersion), C.c_double, C.c_
 _L.rich_last_error.restype = C.c_char_p
 _L.rich_version.restype = C.c_char_p
 for _f in ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params", "rich_propagate",
-           "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_get_status",
+           "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint", "rich_propagate_adjoint_noalloc",
+           "rich_get_status",
            "rich_cherenkov_yield", "rich_film_readout", "rich_fit_step"):
     getattr(_L, _f).restype = C.c_int32
 
 EXPORTED = ("rich_build_scene", "rich_destroy_scene", "rich_scene_info", "rich_set_mirror_params",
             "rich_propagate", "rich_propagate_batch", "rich_autotune", "rich_propagate_adjoint",
+            "rich_propagate_adjoint_noalloc",
             "rich_get_status", "rich_cherenkov_yield", "rich_film_readout", "rich_fit_step", "rich_last_error",
             "rich_version")
 
@@ -229,6 +232,15 @@ def rich_propagate_adjoint(handle, source, batch, n_photons, seed, first_photon_
                                      int(first_photon_id), _ptr(dev_grad_uv), _ptr(dev_targets), _ptr(dev_mask),
                                      _ptr(dev_residual_cut), _ptr(dev_grad_params), _ptr(dev_loss),
                                      _stream(stream)))
+
+
+def rich_propagate_adjoint_noalloc(handle, source, batch, n_photons, seed, first_photon_id, dev_grad_uv,
+                                   dev_targets, dev_mask, dev_residual_cut, dev_grad_params, dev_loss, stream=None):
+    _check(_L.rich_propagate_adjoint_noalloc(handle, None if source is None else C.byref(source),
+                                             None if batch is None else C.byref(batch), int(n_photons), int(seed),
+                                             int(first_photon_id), _ptr(dev_grad_uv), _ptr(dev_targets),
+                                             _ptr(dev_mask), _ptr(dev_residual_cut), _ptr(dev_grad_params),
+                                             _ptr(dev_loss), _stream(stream)))
 
 
 def rich_fit_step(handle, fit, dev_p0, dev_grad, dev_loss, dev_state, dev_params, dev_losses, dev_cut, stream=None):
