@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-forms", action="store_true", help="only the headline workload")
-    p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large", help="comma list of extra forms")
+    p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large,largefit", help="comma list of extra forms")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
@@ -90,6 +90,7 @@ def cpu_baseline(cfg, target_seconds):
     """FP64 oracle on a bounded prefix of the same workload, all host threads (up to 16)."""
     import numpy as np
     from oracle import oracle as O
+    from paper_2309_12496_amd import inputs as I
     threads = min(os.cpu_count() or 1, 16)
     sc = O.Scene(cfg["scene"])
     probe = 20000
@@ -106,10 +107,21 @@ def cpu_baseline(cfg, target_seconds):
     t0 = time.perf_counter()
     O.propagate(sc, cfg["source"], n1, cfg["seed"], threads=1)
     dt1 = time.perf_counter() - t0
+    # the analytic workload: all of its 1e5 photons, on every thread and on one
+    c1 = I.config(1)
+    sc1 = O.Scene(c1["scene"])
+    c1_rates = {}
+    for th in (threads, 1):
+        t0 = time.perf_counter()
+        O.propagate(sc1, c1["source"], c1["n_photons"], c1["seed"], threads=th)
+        c1_rates[th] = c1["n_photons"] / (time.perf_counter() - t0)
     return {"value": n / dt, "unit": "photons/s", "cores": threads, "kind": "oracle",
             "sample": f"photon ids 0..{n - 1} of the headline workload ({dt:.1f} s on {threads} threads)",
             "single_thread": {"value": n1 / dt1, "unit": "photons/s",
-                              "sample": f"photon ids 0..{n1 - 1} ({dt1:.1f} s on 1 thread)"}}
+                              "sample": f"photon ids 0..{n1 - 1} ({dt1:.1f} s on 1 thread)"},
+            "analytic": {"workload": c1["name"], "sample": f"all {c1['n_photons']} photons",
+                         "photons_per_s": c1_rates[threads], "threads": threads,
+                         "single_thread_photons_per_s": c1_rates[1]}}
 
 
 def form_batched(R, I, stream, steps):
@@ -159,28 +171,38 @@ def _fwd_adjoint(R, I, cfg, stream, steps):
             "tuning": {"block": tune.block, "chunk": tune.chunk, "blocks_per_cu": tune.blocks_per_cu}}
 
 
-def form_align_fit(R, I, stream, steps):
-    """Adam alignment fit of the segmented mirror: one set_params + one fused adjoint launch per step.
+def form_align_fit(R, I, stream, steps, k=4):
+    """Adam alignment fit of the segmented mirror: one fused adjoint launch and one device Adam step
+    (which also moves the mirrors) per step, captured once in a graph and replayed.
 
     Targets are the device hits at the seeded misalignment; the fit starts from
-    the nominal geometry.  Reports the step rate and how far the fitted tilts
-    and radii are from the misalignment, over the segments the photons reach
-    (the only ones whose parameters move).
+    the nominal geometry.  k = 4: the analytic 4 x 4 mirror on its 1e6 photons,
+    tilts and radii; k = 5: the 2M-triangle large scene, its 8192 tracks thinned
+    to 1221 photons each (1.0e7), tilts only (a meshed segment's radius scales it
+    about its pivot, which keeps every facet normal).  Reports the step rate over
+    the photons a step retraces (the mask: those the target run detected) and
+    how far the fitted tilts and radii are from the misalignment, over the
+    segments the photons reach (the only ones whose parameters move).
     """
     import numpy as np
     import torch
-    from paper_2309_12496_amd.align import fit_alignment
-    cfg = I.config(4)
+    from paper_2309_12496_amd.align import FIT_TILTS_RADII, fit_alignment
+    cfg = I.config(k)
+    if k == 5:
+        src = I.batch_source(cfg["source"]["tracks"], np.full(len(cfg["source"]["tracks"]), 1221))
+        free, what = (True, True, False, False, False, False), "tilts"
+    else:
+        src, free, what = cfg["source"], FIT_TILTS_RADII, "tilts and radii"
     sc = R.Scene(cfg["scene"])
     sc.set_params(cfg["target_params"])
-    tgt = R.propagate_batch(sc, cfg["source"], cfg["seed"], tune=R.tuning(256, 256, 4))
+    tgt = R.propagate_batch(sc, src, cfg["seed"], tune=R.tuning(256, 256, 4))
     on = tgt["fate"] <= R.QE_REJECTED
     uv = tgt["hit_uv"].nan_to_num(0.0)
     del tgt
-    fit_alignment(sc, cfg["source"], cfg["seed"], uv, on, steps=3)          # warm-up
+    fit_alignment(sc, src, cfg["seed"], uv, on, steps=3, free=free)          # warm-up
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    p, losses = fit_alignment(sc, cfg["source"], cfg["seed"], uv, on, steps=steps, lr=0.3)
+    p, losses = fit_alignment(sc, src, cfg["seed"], uv, on, steps=steps, lr=0.3, free=free)
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
@@ -189,15 +211,17 @@ def form_align_fit(R, I, stream, steps):
     p0 = np.asarray(cfg["scene"]["params"], np.float32).astype(np.float64)
     tp = np.asarray(cfg["target_params"], np.float64)
     moved = np.any(p != p0, axis=1)
-    # a step retraces only the photons of the mask (those the target run detected)
+    tilt_err = np.abs(p[moved, :2] - tp[moved, :2]).max(axis=1)
     traced = int(on.sum())
-    return {"workload": cfg["name"] + ", Adam fit of tilts and radii from the nominal geometry",
-            "emitted_photons": cfg["n_photons"], "traced_photons_per_step": traced, "steps": steps,
-            "ms_per_step": ms, "traced_photons_per_s": traced / (ms * 1e-3),
-            "loss_first_mm2": float(losses[0]), "loss_last_mm2": float(losses[-1]),
-            "segments_fitted": int(moved.sum()),
-            "max_tilt_error_rad": float(np.abs(p[moved, :2] - tp[moved, :2]).max()),
-            "max_radius_error_mm": float(np.abs(p[moved, 2] - tp[moved, 2]).max())}
+    out = {"workload": f"{cfg['name']}, Adam fit of {what} from the nominal geometry",
+           "emitted_photons": int(src["offsets"][-1]), "traced_photons_per_step": traced, "steps": steps,
+           "ms_per_step": ms, "traced_photons_per_s": traced / (ms * 1e-3),
+           "loss_first_mm2": float(losses[0]), "loss_last_mm2": float(losses[-1]),
+           "segments_fitted": int(moved.sum()), "max_tilt_error_rad": float(tilt_err.max()),
+           "tilt_error_rad_by_segment": [float(f"{x:.3g}") for x in np.sort(tilt_err)[::-1]]}
+    if free[2]:
+        out["max_radius_error_mm"] = float(np.abs(p[moved, 2] - tp[moved, 2]).max())
+    return out
 
 
 def form_prefilter(R, I, stream, steps):
@@ -222,6 +246,13 @@ def form_c1(R, I, stream, steps):
     n = cfg["n_photons"]
     t, o = R.alloc_outputs(sc, n)
     ms = time_steps(lambda: R.rich_propagate(sc.handle, s, n, cfg["seed"], 0, o, stream), steps, 3, stream)
+    # the same call captured once in a HIP graph and replayed (fate counts and
+    # histogram accumulate over the replays; per-photon outputs are rewritten)
+    import torch
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        R.rich_propagate(sc.handle, s, n, cfg["seed"], 0, o, torch.cuda.current_stream())
+    msg = time_steps(graph.replay, steps, 3, stream)
     big = 100_000_000
     tb, ob = R.alloc_outputs(sc, big)
     msb = time_steps(lambda: R.rich_propagate(sc.handle, s, big, cfg["seed"], 0, ob, stream), max(3, steps // 4), 1,
@@ -229,6 +260,7 @@ def form_c1(R, I, stream, steps):
     assert sc.status() == 0
     return {"workload": cfg["name"], "single_call": {"photons_per_step": n, "ms_per_step": ms,
                                                       "photons_per_s": n / (ms * 1e-3)},
+            "graph_replay": {"photons_per_step": n, "ms_per_step": msg, "photons_per_s": n / (msg * 1e-3)},
             "steady_state": {"photons_per_step": big, "ms_per_step": msb, "photons_per_s": big / (msb * 1e-3)}}
 
 
@@ -303,6 +335,8 @@ def main():
             forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half)
         if "fit" in want:
             forms["align_fit"] = form_align_fit(R, I, stream, 300)
+        if "largefit" in want:
+            forms["large_align_fit"] = form_align_fit(R, I, stream, 300, k=5)
         if "prefilter" in want:
             forms["prefilter"] = form_prefilter(R, I, stream, half)
         if "large" in want:
