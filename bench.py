@@ -35,10 +35,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
-# VALU work per photon of forward_kernel on the headline workload, in 32-bit
-# lane operations: SQ_INSTS_VALU x 64 lanes / photons = 1.10301e9 x 64 / 1e7
-# (profiles/forward_kernel_c2_counters.md).  Issued slots, inactive lanes included.
-ALU_OPS_PER_PHOTON = 7059.3
+# Algorithmic VALU work per photon of the headline workload, in 32-bit lane
+# operations: the method's units of work per photon counted on the GPU by the
+# measurement build (26.27 BVH4 nodes, 10.19 triangle tests, 3.72 leaves,
+# 6.48 instance entries, 2.78 closest-hit queries, 1.78 reflections, 0.85
+# detector hits, 2 Philox blocks) times the operations each takes
+# (paper_2309_12496_amd/work_counts.py; profiles/work_counts.md).
+ALU_OPS_PER_PHOTON = 3458.0
+# What forward_kernel executes per photon on the same workload (rocprofv3,
+# profiles/forward_kernel_c2_counters.md): SQ_INSTS_VALU x 64 / photons =
+# issued lane slots (inactive lanes of divergent waves included), and
+# SQ_THREAD_CYCLES_VALU / photons = lane operations of active lanes (the
+# counter reads 64 per instruction on a plain copy kernel).
+ISSUED_SLOTS_PER_PHOTON = 7059.3
+ACTIVE_LANE_OPS_PER_PHOTON = 5067.6
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
@@ -55,6 +65,9 @@ def parse():
     p.add_argument("--no-forms", action="store_true", help="only the headline workload")
     p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large,largefit", help="comma list of extra forms")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    p.add_argument("--fixed-tuning", action="store_true",
+                   help="batch forms use block 256, chunk 256, 4 blocks per CU instead of the autotuner "
+                        "(for profiler runs, which would otherwise trace the autotuner's sweep)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device copy (to scale FETCH_SIZE/WRITE_SIZE counters)")
     return p.parse_args()
@@ -124,14 +137,14 @@ def cpu_baseline(cfg, target_seconds):
                          "single_thread_photons_per_s": c1_rates[1]}}
 
 
-def form_batched(R, I, stream, steps):
+def form_batched(R, I, stream, steps, fixed_tuning=False):
     cfg = I.config(3)
     t0 = time.perf_counter()
     sc = R.Scene(cfg["scene"])
     build_s = time.perf_counter() - t0
     b, keep, n = R.make_batch(cfg["source"])
     t, o = R.alloc_outputs(sc, n)
-    tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])
+    tune = R.tuning(256, 256, 4) if fixed_tuning else R.rich_autotune(sc.handle, b, n, cfg["seed"])
     ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 2, stream)
     assert sc.status() == 0
     return {"workload": cfg["name"], "photons_per_step": n, "ms_per_step": ms, "photons_per_s": n / (ms * 1e-3),
@@ -139,14 +152,15 @@ def form_batched(R, I, stream, steps):
             "scene_build_s": round(build_s, 3)}
 
 
-def _fwd_adjoint(R, I, cfg, stream, steps):
+def _fwd_adjoint(R, I, cfg, stream, steps, fixed_tuning=False):
     """Forward (batched) plus fused-loss adjoint per step, targets from misaligned segments."""
     import torch
     t0 = time.perf_counter()
     sc = R.Scene(cfg["scene"])
     build_s = time.perf_counter() - t0
     b, keep, n = R.make_batch(cfg["source"])
-    tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])      # the launch shape a caller gets with tune=NULL
+    # the autotuned shape is what a caller gets with tune=NULL
+    tune = R.tuning(256, 256, 4) if fixed_tuning else R.rich_autotune(sc.handle, b, n, cfg["seed"])
     sc.set_params(cfg["target_params"])
     tgt_out = R.propagate_batch(sc, cfg["source"], cfg["seed"], tune=tune)
     targets = tgt_out["hit_uv"].nan_to_num(0.0)
@@ -297,8 +311,15 @@ def main():
 
     if ALU_OPS_PER_PHOTON:
         achieved = ALU_OPS_PER_PHOTON * n / (ms * 1e-3)
+        rate = n / (ms * 1e-3)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+                "algorithmic_ops_per_photon": ALU_OPS_PER_PHOTON,
+                # the same peak in the datasheet's units: 78.6 TFLOP/s counting an FMA as two
+                # operations, 157.3 with packed FP32 (not used: the build disables it)
+                "fp32_fma_tflops_peak": 78.6, "fp32_packed_tflops_peak": 157.3,
+                "issue_frac": ISSUED_SLOTS_PER_PHOTON * rate / VALU_PEAK_LANE_OPS,
+                "active_lane_frac": ACTIVE_LANE_OPS_PER_PHOTON * rate / VALU_PEAK_LANE_OPS,
                 "traffic": None if TRAFFIC_BYTES_PER_PHOTON is None else TRAFFIC_BYTES_PER_PHOTON * n}
     else:
         gbs = OUT_BYTES_PER_PHOTON * n / (ms * 1e-3) / 1e9
@@ -330,9 +351,9 @@ def main():
         if "c1" in want:
             forms["analytic"] = form_c1(R, I, stream, args.steps)
         if "batched" in want:
-            forms["batched"] = form_batched(R, I, stream, half)
+            forms["batched"] = form_batched(R, I, stream, half, args.fixed_tuning)
         if "adjoint" in want:
-            forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half)
+            forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half, args.fixed_tuning)
         if "fit" in want:
             forms["align_fit"] = form_align_fit(R, I, stream, 300)
         if "largefit" in want:
@@ -340,7 +361,7 @@ def main():
         if "prefilter" in want:
             forms["prefilter"] = form_prefilter(R, I, stream, half)
         if "large" in want:
-            forms["large_fwd_adjoint"] = _fwd_adjoint(R, I, I.config(5), stream, 3)
+            forms["large_fwd_adjoint"] = _fwd_adjoint(R, I, I.config(5), stream, 3, args.fixed_tuning)
         line["forms"] = forms
         torch.cuda.empty_cache()
     if not args.no_cpu:

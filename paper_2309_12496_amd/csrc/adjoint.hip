@@ -220,6 +220,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
         // detector plane
         V3 gP = v3(0.0f, 0.0f, 0.0f), gD = v3(0.0f, 0.0f, 0.0f);
         if (act) {
+            work(kWorkBackDetector);
             V3 gPd = fma3(gu, ld3(det.u), gv * ld3(det.v));
             gP = plane_back(gPd, rec.det_d, ld3(det.n));
             gD = rec.det_t * gP;
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
                 V3 gDin = fma3(-2.0f * gdn, x.n, gD);
                 V3 gO;
                 if (x.kind == kKindCap) {
+                    work(kWorkBackCaps);
                     const CapDev &cp = S.caps[x.idx];
                     float invR = 1.0f / cp.R;
                     V3 w = x.P - ld3(cp.C);
@@ -252,6 +254,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
                     gp[4] = gC.y;
                     gp[5] = gC.z;
                 } else if (x.kind == kKindFacet) {
+                    work(kWorkBackFacets);
                     const Instance &in = S.inst[x.inst];
                     const Tri &tr = S.tris[x.idx];
                     V3 vl = ld3(tr.v0), nl = ld3(tr.n);
@@ -269,6 +272,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(DevScene S, DevSourc
                     gp[4] = gq.y;
                     gp[5] = gq.z;
                 } else {
+                    work(kWorkBackPlanes);
                     gO = plane_back(gP, x.d, x.n);
                 }
                 gP = gO;
@@ -354,3 +358,19 @@ hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const Adjoint
 }
 
 }  // namespace rich
+
+#ifdef RICH_WORK_COUNTERS
+// Measurement build only: the adjoint kernel's work counters (this file's
+// copy), as rich_work_counters gives the forward and batch kernels'.
+extern "C" int rich_work_counters_adjoint(unsigned long long *out, int reset) {
+    unsigned long long raw[16 * rich::kWorkUnits];
+    if (hipDeviceSynchronize() != hipSuccess) return -3;
+    if (hipMemcpyFromSymbol(raw, HIP_SYMBOL(rich::rich_work), sizeof raw) != hipSuccess) return -3;
+    for (int u = 0; u < rich::kWorkUnits; ++u) out[u] = raw[16 * u];
+    if (reset) {
+        unsigned long long zero[16 * rich::kWorkUnits] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(rich::rich_work), zero, sizeof zero) != hipSuccess) return -3;
+    }
+    return 0;
+}
+#endif

@@ -321,6 +321,7 @@ constexpr int kForwardBlocksPerCu = 8;
 __device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSource &src, uint64_t seed, uint64_t g,
                                                 uint64_t i, uint32_t bins) {
     const uint32_t top = bins - 1u;
+    work(kWorkSortKeys);
     const uint4 w = photon_block(seed, g, 0);
     if (src.prefilter && src.n_disp == 0 && src.kind != 2) {
         // the wavelength alone decides (with dispersion or explicit photons
@@ -512,3 +513,20 @@ hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutput
 }
 
 }  // namespace rich
+
+#ifdef RICH_WORK_COUNTERS
+// Measurement build only: copy the forward and batch kernels' work counters
+// (WorkUnit order, kWorkUnits values) to the host, then zero them when reset
+// is set.  Synchronises the current device.
+extern "C" int rich_work_counters(unsigned long long *out, int reset) {
+    unsigned long long raw[16 * rich::kWorkUnits];
+    if (hipDeviceSynchronize() != hipSuccess) return -3;
+    if (hipMemcpyFromSymbol(raw, HIP_SYMBOL(rich::rich_work), sizeof raw) != hipSuccess) return -3;
+    for (int u = 0; u < rich::kWorkUnits; ++u) out[u] = raw[16 * u];
+    if (reset) {
+        unsigned long long zero[16 * rich::kWorkUnits] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(rich::rich_work), zero, sizeof zero) != hipSuccess) return -3;
+    }
+    return 0;
+}
+#endif

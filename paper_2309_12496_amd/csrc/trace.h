@@ -41,6 +41,32 @@ __device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k ==
 // vector load per lane.  Without it, any output store earlier in the kernel
 // keeps the compiler from proving the data unchanged.
 #define RICH_CONST __attribute__((address_space(4)))
+
+// Work counters of the measurement build (compiled with -DRICH_WORK_COUNTERS;
+// the product library has none of this).  Each counts one unit of work per
+// active lane: a traced photon, a Philox block (of which the regrouping's
+// second draw of block 0 for its sort key is also counted apart), a
+// closest-hit query (ray set-up and the detector plane), a cap's bounding-box
+// test and its sphere test, a rectangle, the analytic box, a BVH4 node whose
+// four child boxes are tested, a leaf, a triangle test, an entry into a mesh
+// instance's frame (and apart those that rotate and scale the ray), a
+// reflection, a detector hit; in the adjoint, a counted photon's pass back
+// through the detector plane and each reflection it sweeps back through (cap
+// or facet).  Lanes of a wave are summed with one atomic per counter and wave.
+enum WorkUnit {
+    kWorkPhotons, kWorkPhilox, kWorkSortKeys, kWorkQueries, kWorkCapBoxes, kWorkCaps, kWorkRects, kWorkBoxes,
+    kWorkNodes, kWorkLeaves, kWorkTris, kWorkInstances, kWorkMovingInstances, kWorkReflections, kWorkDetections,
+    kWorkBackDetector, kWorkBackCaps, kWorkBackFacets, kWorkBackPlanes, kWorkUnits
+};
+#ifdef RICH_WORK_COUNTERS
+static __device__ unsigned long long rich_work[16 * kWorkUnits];   // one 128-byte line per counter
+__device__ __forceinline__ void work(int unit) {
+    const unsigned long long m = __ballot(1);
+    if (__lane_id() == __ffsll((long long)m) - 1) atomicAdd(&rich_work[16 * unit], (unsigned long long)__popcll(m));
+}
+#else
+__device__ __forceinline__ void work(int) {}
+#endif
 template <class T>
 __device__ __forceinline__ const RICH_CONST T &cref(const T &x) {
     return *(const RICH_CONST T *)&x;
@@ -65,6 +91,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 
 __device__ __forceinline__ uint4 photon_block(uint64_t seed, uint64_t g, uint32_t blk) {
+    work(kWorkPhilox);
     return philox4x32_10(make_uint4((uint32_t)g, (uint32_t)(g >> 32), blk, kStreamTag), (uint32_t)seed,
                          (uint32_t)(seed >> 32));
 }
@@ -424,6 +451,7 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
     const float tmin = S.t_min;
     while (true) {
         if (!(ref & kLeafBit)) {
+            work(kWorkNodes);
             // near/far planes per axis follow the direction signs; 32-bit byte
             // offsets from the uniform base keep the address arithmetic scalar
             const char *nb = reinterpret_cast<const char *>(S.nodes);
@@ -482,10 +510,12 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
                 atomicOr(S.status, 2u);
             } else {
                 stk[(sp++) * stride] = kExitMarker;
+                work(kWorkInstances);
                 const Instance &in = S.inst[k];
                 if (in.segment < 0) {
                     set_origin(r, ow - ld3(in.org));   // fixed instances only translate
                 } else {
+                    work(kWorkMovingInstances);
                     ray_setup(r, mat3(in.m, ow - ld3(in.org)), mat3(in.m, dw));
                     moved = true;
                 }
@@ -496,8 +526,10 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
         } else {
             uint32_t first = ref & 0x07FFFFFFu;
             uint32_t cnt = ((ref >> 27) & 7u) + 1u;
+            work(kWorkLeaves);
             const Shear sh = make_shear(r.d);
             for (uint32_t q = first; q < first + cnt; ++q) {
+                work(kWorkTris);
                 const char *tb = reinterpret_cast<const char *>(S.tris) + (q << 6);
                 float4 a = *reinterpret_cast<const float4 *>(tb);
                 float4 b = *reinterpret_cast<const float4 *>(tb + 16);
@@ -533,7 +565,9 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 
     float t;
     for (int i = 0; i < S.n_caps; ++i) {
         const RICH_CONST CapDev &cp = cref(S.caps[i]);
+        work(kWorkCapBoxes);
         if (slab_entry(r, cp.lo[0], cp.lo[1], cp.lo[2], cp.hi[0], cp.hi[1], cp.hi[2], h.t) == INFINITY) continue;
+        work(kWorkCaps);
         int root;
         if (hit_cap(cp, o, d, tmin, t, root) && better(t, (uint32_t)i, h)) {
             h.t = t;
@@ -543,6 +577,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 
     }
     for (int i = 0; i < S.n_rects; ++i) {
         const RICH_CONST RectDev &rc = cref(S.rects[i]);
+        work(kWorkRects);
         if (hit_plane_rect(ld3(rc.c), ld3(rc.n), ld3(rc.u), ld3(rc.v), rc.hu, rc.hv, o, d, tmin, t) &&
             better(t, (uint32_t)(S.n_caps + i), h)) {
             h.t = t;
@@ -554,6 +589,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 
         h.t = t;
         h.prim = S.prim_det;
     }
+    if (S.has_box) work(kWorkBoxes);
     if (S.has_box && hit_box(S.box_lo, S.box_hi, r, tmin, t) && better(t, S.prim_box, h)) {
         h.t = t;
         h.prim = S.prim_box;
@@ -639,8 +675,10 @@ __device__ __forceinline__ void propagate(const DevScene &S, const D &det, const
     uint4 blk = make_uint4(0, 0, 0, 0);
     int have = -1;
     float clock = ph.t0;        // time at the start of the current segment (ns)
+    work(kWorkPhotons);
     for (int b = 0; b < S.max_bounces; ++b) {
         Hit h;
+        work(kWorkQueries);
         closest_hit(S, det, o, d, h, stk, stride);
         if (h.prim == 0xFFFFFFFFu) {
             end.fate = kEscaped;
@@ -663,6 +701,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const D &det, const
             end.u = u;
             end.v = v;
             end.time = fmaf(h.t, ph.ng_c, clock);
+            work(kWorkDetections);
             rec.detect(b, o, d, h.t);
             if (efficiencies) {
                 float qe = lerp_table(det.n_qe, det.qe_x, det.qe_y, det.qe_s, ph.lambda);
@@ -697,6 +736,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const D &det, const
                 break;
             }
         }
+        work(kWorkReflections);
         rec.reflect(b, h, o, d, P, n);
         clock = fmaf(h.t, ph.ng_c, clock);
         V3 dr = fma3(-2.0f * dot(d, n), n, d);

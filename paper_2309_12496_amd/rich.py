@@ -18,7 +18,9 @@ import numpy as np
 import torch  # loads the HIP runtime that librich shares with torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librich.so")
+# RICH_LIBRARY selects another build of the same ABI (the work-counting
+# measurement build, librich_work.so); the default is librich.so.
+LIB_PATH = os.environ.get("RICH_LIBRARY") or os.path.join(HERE, "librich.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2309_12496_amd.build_lib`")
