@@ -395,17 +395,19 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving or fitting loops, harnesses that forbid hipMalloc):
  * rich_propagate_adjoint with the same arguments, results and errors, except
- * that its block partial sums live in a static device array that the library
- * holds on every device it runs on (8 MiB, 2^21 floats, kept until the
- * process ends) instead of the scene's buffer, so it never calls hipMalloc
- * or hipFree.  The partial sums take B x (6 n_segments + 2) floats with
- * B = min(ceil(n_photons / 2048), 16 x compute units); a call that needs more
- * than 2^21 returns RICH_ERANGE before launching anything (on a 256-CU
- * MI355X, any photon count works up to 85 segments).  Every call on one
- * device shares that device's array: calls that overlap on one device
+ * that its device work buffer lives in a static device array that the
+ * library holds on every device it runs on (8 MiB, kept until the process
+ * ends) instead of the scene's buffer, so it never calls hipMalloc or hipFree.
+ * The work buffer holds B x (6 n_segments + 2) floats of block partial sums
+ * per 2^32 photons (B = min(ceil(n / 4096), the blocks the device holds at
+ * once)) and, with a mask, 12 bytes per 4096 photons of mask counts, each
+ * part rounded up to 256 bytes; a call that needs more than 8 MiB returns
+ * RICH_ERANGE before launching anything (on MI355X: up to 256 segments with
+ * up to 1.7e9 masked-call photons, or 2^32 without a mask).  Every call on
+ * one device shares that device's array: calls that overlap on one device
  * (different streams, or different host threads) race and give wrong sums;
  * order them on one stream.  The array needs no clearing: each launch writes
- * every partial it later reads. */
+ * every value it later reads. */
 rich_status rich_propagate_adjoint_noalloc(rich_scene *s, const rich_source *src, const rich_batch *batch,
                                            uint64_t n_photons, uint64_t seed, uint64_t first_photon_id,
                                            const float *dev_grad_uv, const float *dev_targets,

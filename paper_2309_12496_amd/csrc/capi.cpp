@@ -520,6 +520,23 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
             }
         }
         DevOutputs dout = make_outputs(out);
+        // Large batches on meshed scenes are processed in an order of the
+        // tracks by direction dealt to the id partitions (each XCD's tracks in
+        // flight then point the same way, and share L2 lines); photon ids and
+        // results do not change.  Small batches do not repay its five launches.
+        const bool ordered = s->dev.has_mesh && n_photons >= (1ull << 21) && batch->n_tracks >= 64;
+        if (ordered) {
+            const size_t need = order_buffer_bytes(batch->n_tracks);
+            if (need > s->order_bytes) {
+                if (s->d_order) (void)hipFree(s->d_order);
+                s->d_order = nullptr;
+                s->order_bytes = 0;
+                if (hipMalloc(&s->d_order, need) != hipSuccess)
+                    return set_error(RICH_ENOMEM, "batch order buffer allocation failed");
+                s->order_bytes = need;
+            }
+            set_order(ds, s->d_order);
+        }
         // the graph is reused while every launch argument is the same: compare
         // their bytes (both structs are zero-filled before they are set)
         std::string k2;
@@ -540,12 +557,14 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
             }
             if (!s->capture_stream) RICH_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
             RICH_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e0 = ordered ? launch_order(ds, batch_parts(grid_of(s, t)), s->d_order, s->capture_stream)
+                                    : hipSuccess;
             hipError_t e1 = launch_fill_u64(s->d_counter, kBatchCounters, s->capture_stream);
             hipError_t e2 = launch_batch(s->dev, ds, dout, n_photons, seed, s->d_counter, t.block, t.chunk,
                                          grid_of(s, t), true, s->capture_stream);
             hipGraph_t gr = nullptr;
             hipError_t e3 = hipStreamEndCapture(s->capture_stream, &gr);
-            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (gr) (void)hipGraphDestroy(gr);
                 return set_error(RICH_EDEVICE, "graph capture failed");
             }
@@ -583,34 +602,33 @@ static rich_status adjoint_call(rich_scene *s, const rich_source *src, const ric
     if (batch && first_photon_id != 0) return set_error(RICH_EINVAL, "batch photons start at id 0");
     DeviceGuard g(s->device);
     int n_par = 6 * s->n_segments;
-    int block = adjoint_block_size();
-    uint64_t per_block = (uint64_t)block * 8;
-    uint64_t nb = (n_photons + per_block - 1) / per_block;
-    int n_blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(nb, (uint64_t)s->n_cu * 16));
-    size_t need = (size_t)n_blocks * (n_par + 2);
-    float *partials = nullptr;
+    const AdjointPlan plan = adjoint_plan(n_photons, n_par, s->n_cu, dev_mask != nullptr);
+    float *work = nullptr;
     if (noalloc) {
-        if (need > kAdjScratchFloats)
+        if (plan.bytes > kAdjScratchFloats * sizeof(float))
             return set_error(RICH_ERANGE,
-                             "no-allocation adjoint: %d blocks x %d floats of partial sums exceed its %zu floats "
+                             "no-allocation adjoint: %zu bytes of partial sums and mask counts exceed its %zu "
                              "(fewer segments or photons, or rich_propagate_adjoint)",
-                             n_blocks, n_par + 2, kAdjScratchFloats);
-        hipError_t e = adjoint_scratch(s->device, &partials);
+                             plan.bytes, kAdjScratchFloats * sizeof(float));
+        hipError_t e = adjoint_scratch(s->device, &work);
         if (e != hipSuccess)
             return set_error(RICH_EDEVICE, "adjoint scratch address: %s", hipGetErrorString(e));
     } else {
+        // grown to the largest call so far: partial sums, mask counts and offsets
+        const size_t need = (plan.bytes + sizeof(float) - 1) / sizeof(float);
         if (need > s->partials_floats) {
             if (s->d_partials) (void)hipFree(s->d_partials);
             s->d_partials = nullptr;
             s->partials_floats = 0;
             if (hipMalloc(&s->d_partials, need * sizeof(float)) != hipSuccess)
-                return set_error(RICH_ENOMEM, "adjoint partials allocation failed");
+                return set_error(RICH_ENOMEM, "adjoint work buffer allocation failed");
             s->partials_floats = need;
         }
-        partials = s->d_partials;
+        work = s->d_partials;
     }
-    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, partials, dev_grad_params, dev_loss, n_par};
-    RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, n_blocks, stream));
+    AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, nullptr, dev_grad_params, dev_loss, n_par,
+                  nullptr, nullptr};
+    RICH_HIP(launch_adjoint(s->dev, ds, a, n_photons, first_photon_id, seed, plan, work, stream));
     return RICH_OK;
 }
 

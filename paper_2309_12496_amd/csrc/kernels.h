@@ -32,24 +32,45 @@ constexpr int kBatchCounters = kBatchParts * kCounterStride;
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, bool whole_batch, hipStream_t st);
 size_t batch_lds_bytes(int block);
+// Processing order of a batch's tracks: by direction (cells of an octahedral
+// map in Morton order), dealt round robin to the n_parts id partitions of the
+// batch kernel, so that every partition (one per XCD) works through the whole
+// acceptance but its tracks in flight point the same way.  Work buffer of
+// order_buffer_bytes(n_tracks) bytes: set_order points src.order and
+// src.order_off into it, launch_order fills them on the stream.
+size_t order_buffer_bytes(int n_tracks);
+void set_order(DevSource &src, void *buffer);
+hipError_t launch_order(const DevSource &src, int n_parts, void *buffer, hipStream_t st);
+int batch_parts(int grid);
 
 struct AdjointArgs {
     const float *grad_uv;       // [N][2] or null
     const float *targets;       // [N][2] or null
     const uint8_t *mask;        // [N] or null (all)
     const float *residual_cut;  // [1] or null (fused-loss mode only)
-    float *partials;            // [n_blocks][n_par + 2]
+    float *partials;            // [rows][n_par + 2], set by launch_adjoint
     float *grad;                // [n_seg][6]
     float *loss;                // [1] or null
     int32_t n_par;
+    uint32_t *chunk_counts;                    // mask given: masked ids per chunk, set by launch_adjoint
+    const unsigned long long *chunk_offsets;   // their exclusive scan, [n_chunks + 1]
 };
+// Device work buffer of one adjoint call: block partial sums (one row of
+// n_par + 2 floats per block and launch segment of up to 2^32 ids), then, with
+// a mask, the per-chunk counts and their scan.
+struct AdjointPlan {
+    int n_blocks;          // blocks of the persistent grid
+    int n_segments;        // launches of up to 2^32 ids
+    uint64_t n_chunks;     // mask chunks of the largest segment (0 without a mask)
+    size_t counts_offset, offsets_offset, bytes;
+};
+AdjointPlan adjoint_plan(uint64_t n, int n_par, int n_cu, bool masked);
 hipError_t launch_adjoint(const DevScene &S, const DevSource &src, const AdjointArgs &a, uint64_t n, uint64_t first,
-                          uint64_t seed, int n_blocks, hipStream_t st);
-int adjoint_block_size();
-// Partial-sum buffer of the no-allocation adjoint entry point: a file-scope
-// device array of kAdjScratchFloats floats (8 MiB) on every device the library
-// runs on.  adjoint_scratch returns its device address on `device`, which
-// must be current; the address is looked up once per device and cached.
+                          uint64_t seed, const AdjointPlan &plan, void *work, hipStream_t st);
+// Work buffer of the no-allocation adjoint entry point: a file-scope device
+// array of kAdjScratchFloats floats (8 MiB) on every device the library runs
+// on.  adjoint_scratch returns its device address on `device`, which must be
+// current; the address is looked up once per device and cached.
 constexpr size_t kAdjScratchFloats = size_t(1) << 21;
 constexpr int kAdjScratchDevices = 64;
 hipError_t adjoint_scratch(int device, float **ptr);

@@ -207,12 +207,13 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
 // VGPRs, spills the extra scalar state and reads the detector per lane.
 template <bool kConstDet>
 __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
-                                          uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride) {
+                                          uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride,
+                                          int track = -1) {
     PathEnd end;
     end.fate = -1;
     end.pixel = -1;
     if (active) {
-        Photon ph = make_photon(src, seed, g, i);
+        Photon ph = make_photon(src, seed, g, i, true, track);
         NoRecord rec;
         auto run = [&](const auto &det) {
             if (!src.prefilter) {
@@ -412,6 +413,160 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- batch: processing order
+
+constexpr int kOrderCellBits = 7;                        // cells per axis: 128
+constexpr int kOrderCells = 1 << (2 * kOrderCellBits);   // 16384
+
+// Cell of a direction: the octahedral map of the unit sphere onto [-1, 1]^2
+// (the lower hemisphere folded outwards), a 128 x 128 grid, cells numbered in
+// Morton order so that neighbouring numbers are neighbouring directions.
+__device__ __forceinline__ uint32_t direction_cell(float x, float y, float z) {
+    const float s = fabsf(x) + fabsf(y) + fabsf(z);
+    float u = s > 0.0f ? x / s : 0.0f, v = s > 0.0f ? y / s : 0.0f;
+    if (z < 0.0f) {
+        const float fu = (1.0f - fabsf(v)) * copysignf(1.0f, u), fv = (1.0f - fabsf(u)) * copysignf(1.0f, v);
+        u = fu;
+        v = fv;
+    }
+    const int n = 1 << kOrderCellBits;
+    const uint32_t iu = (uint32_t)min(max((int)((u + 1.0f) * 0.5f * n), 0), n - 1);
+    const uint32_t iv = (uint32_t)min(max((int)((v + 1.0f) * 0.5f * n), 0), n - 1);
+    uint32_t m = 0;
+    for (int b = 0; b < kOrderCellBits; ++b) m |= (((iu >> b) & 1u) << (2 * b)) | (((iv >> b) & 1u) << (2 * b + 1));
+    return m;
+}
+
+__global__ void order_cells_kernel(const float *tracks, int n_tracks, uint32_t *hist, uint32_t *cell_of) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tracks) return;
+    const float4 *tr = reinterpret_cast<const float4 *>(tracks) + 2 * t;
+    const float4 a = tr[0], b = tr[1];
+    const uint32_t c = direction_cell(a.w, b.x, b.y);
+    cell_of[t] = c;
+    atomicAdd(hist + c, 1u);
+}
+
+// In place: counts per cell -> first position of each cell (one block).
+__global__ __launch_bounds__(1024) void order_scan_cells_kernel(uint32_t *hist) {
+    __shared__ uint32_t part[1024];
+    constexpr int per = kOrderCells / 1024;
+    const int t = threadIdx.x;
+    uint32_t v[per], sum = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        v[j] = hist[t * per + j];
+        sum += v[j];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t y = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        hist[t * per + j] = run;
+        run += v[j];
+    }
+}
+
+// Track t takes the next position of its cell (order within a cell is that of
+// the atomics: it does not change any photon's result), and position pos goes
+// to partition pos mod parts: order[] lists partition 0's tracks, then 1's, ...
+__global__ void order_scatter_kernel(const uint32_t *cell_of, uint32_t *cursor, int n_tracks, int parts,
+                                     int32_t *order) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tracks) return;
+    const uint32_t pos = atomicAdd(cursor + cell_of[t], 1u);
+    const uint32_t c = pos % (uint32_t)parts, per = (uint32_t)n_tracks / (uint32_t)parts;
+    const uint32_t rem = (uint32_t)n_tracks % (uint32_t)parts;
+    order[c * per + min(c, rem) + pos / (uint32_t)parts] = t;
+}
+
+// order_off[q] = photons of the tracks before position q (one block).
+__global__ __launch_bounds__(1024) void order_offsets_kernel(const int32_t *order, const uint64_t *offsets,
+                                                             int n_tracks, uint64_t *order_off) {
+    __shared__ unsigned long long part[1024];
+    const int t = threadIdx.x;
+    const int per = (n_tracks + 1023) / 1024;
+    const int lo = min(t * per, n_tracks), hi = min(lo + per, n_tracks);
+    unsigned long long sum = 0;
+    for (int q = lo; q < hi; ++q) sum += offsets[order[q] + 1] - offsets[order[q]];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        unsigned long long y = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    unsigned long long run = part[t] - sum;
+    for (int q = lo; q < hi; ++q) {
+        order_off[q] = run;
+        run += offsets[order[q] + 1] - offsets[order[q]];
+    }
+    if (t == 1023) order_off[n_tracks] = part[1023];
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t order_buffer_bytes(int n_tracks) {
+    return align256((size_t)kOrderCells * 4) + align256((size_t)n_tracks * 4) + align256((size_t)n_tracks * 4) +
+           ((size_t)n_tracks + 1) * 8;
+}
+
+void set_order(DevSource &src, void *buffer) {
+    const int T = src.n_tracks;
+    char *b = static_cast<char *>(buffer);
+    src.order = reinterpret_cast<const int32_t *>(b + align256((size_t)kOrderCells * 4) + align256((size_t)T * 4));
+    src.order_off =
+        reinterpret_cast<const uint64_t *>(b + align256((size_t)kOrderCells * 4) + 2 * align256((size_t)T * 4));
+}
+
+hipError_t launch_order(const DevSource &src, int n_parts, void *buffer, hipStream_t st) {
+    const int T = src.n_tracks;
+    char *b = static_cast<char *>(buffer);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(b);
+    uint32_t *cell_of = reinterpret_cast<uint32_t *>(b + align256((size_t)kOrderCells * 4));
+    int32_t *order = const_cast<int32_t *>(src.order);
+    uint64_t *order_off = const_cast<uint64_t *>(src.order_off);
+    hipError_t e = launch_fill_u64(reinterpret_cast<unsigned long long *>(hist), kOrderCells / 2, st);
+    if (e != hipSuccess) return e;
+    const int blocks = (T + 255) / 256;
+    hipLaunchKernelGGL(order_cells_kernel, dim3(blocks), dim3(256), 0, st, src.tracks, T, hist, cell_of);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(order_scan_cells_kernel, dim3(1), dim3(1024), 0, st, hist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)cell_of, hist, T,
+                       n_parts, order);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(1024), 0, st, (const int32_t *)order, src.offsets, T,
+                       order_off);
+    return hipGetLastError();
+}
+
+// Photon id of processing position v of a batch: v itself in id order, else
+// the photon v - order_off[k] of the k-th track in processing order, whose
+// index goes to `track` (-1 when unknown: make_photon then searches).  When n
+// is not the tracks' photon total the order is not used (ids beyond it are
+// drawn from the last track, as in id order).
+__device__ __forceinline__ uint64_t batch_photon_id(const DevSource &src, uint64_t v, uint64_t n, int &track) {
+    track = -1;
+    if (!src.order) return v;
+    const RICH_CONST uint64_t *oo = (const RICH_CONST uint64_t *)src.order_off;
+    if (oo[src.n_tracks] != n || v >= n) return v;
+    const int k = find_track_wave(src.order_off, src.n_tracks, v);
+    const int t = src.order[k];
+    const uint64_t g = src.offsets[t] + (v - oo[k]);
+    if (g >= n) return v;   // offsets that do not rise (bad input) never send a write out of range
+    track = t;
+    return g;
+}
+
 // ---------------------------------------------------------------- batch: persistent, dynamic chunks
 
 // Each wave repeatedly claims `chunk` consecutive photon ids from a global
@@ -434,11 +589,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     if (whole_batch && blockIdx.x == 0 && threadIdx.x == 0 && src.offsets[src.n_tracks] != n)
         atomicOr(S.status, 8u);  // RICH_FLAG_BATCH_SIZE: n is not the photon total of the tracks
-    // The id range is cut into n_parts contiguous partitions of `part` ids
-    // (a multiple of the chunk); block b claims chunks of partition b mod
-    // n_parts from that partition's own counter.  Blocks are dispatched to the
-    // 8 XCDs round robin, so with 8 partitions each XCD works through its own
-    // run of tracks and its L2 holds their geometry only.
+    // The processing positions 0..n-1 (photon ids, or with a processing order
+    // its positions) are cut into n_parts contiguous partitions of `part`
+    // positions (a multiple of the chunk); block b claims chunks of partition
+    // b mod n_parts from that partition's own counter.  Blocks are dispatched
+    // to the 8 XCDs round robin, so with 8 partitions each XCD works through
+    // its own run of tracks and its L2 holds their geometry only.
     const int xp = (int)(blockIdx.x % (unsigned)n_parts);
     unsigned long long *ctr = counter + kCounterStride * xp;
     const uint64_t p_lo = (uint64_t)xp * part;
@@ -465,8 +621,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 uint32_t bin[per], rank[per];
                 for (int j = 0; j < per; ++j) {
-                    const uint64_t g = base + (uint64_t)(k + j * 64 + lane);
-                    bin[j] = g < n ? regroup_bin(S, src, seed, g, g, 64u) : 63u;
+                    const uint64_t v = base + (uint64_t)(k + j * 64 + lane);
+                    int tk = -1;
+                    const uint64_t g = v < n ? batch_photon_id(src, v, n, tk) : v;
+                    bin[j] = v < n ? regroup_bin(S, src, seed, g, g, 64u) : 63u;
                     rank[j] = atomicAdd(wbins + bin[j], 1u);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -484,8 +642,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
             }
             for (int j = 0; j < group; j += 64) {
                 const uint32_t off = regroup ? wperm[j + lane] : (uint32_t)(j + lane);
-                const uint64_t g = base + (uint64_t)k + off;
-                int fate = photon_job<false>(S, src, out, g < n, g, g, seed, stk, blockDim.x);
+                const uint64_t v = base + (uint64_t)k + off;
+                int tk = -1;
+                const uint64_t g = v < n ? batch_photon_id(src, v, n, tk) : v;
+                int fate = photon_job<false>(S, src, out, v < n, g, g, seed, stk, blockDim.x, tk);
                 if (out.fate_counts) tally_wave(cnt, fate);
             }
             if (regroup) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -501,10 +661,12 @@ size_t batch_lds_bytes(int block) {
            (size_t)(block / 64) * (kWaveGroup + 64) * sizeof(uint32_t);
 }
 
+int batch_parts(int grid) { return (grid >= kBatchParts && grid % kBatchParts == 0) ? kBatchParts : 1; }
+
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,
                         unsigned long long *counter, int block, int chunk, int grid, bool whole_batch, hipStream_t st) {
     size_t lds = batch_lds_bytes(block);
-    const int n_parts = (grid >= kBatchParts && grid % kBatchParts == 0) ? kBatchParts : 1;
+    const int n_parts = batch_parts(grid);
     const uint64_t per = (n + n_parts - 1) / n_parts;
     const uint64_t part = (per + chunk - 1) / chunk * chunk;
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds, st, S, src, out, n, seed, counter, chunk,

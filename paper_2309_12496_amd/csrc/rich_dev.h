@@ -174,6 +174,11 @@ struct DevSource {
     const float *tracks;        // rich_track[] as 8 floats
     const uint64_t *offsets;
     int32_t n_tracks;
+    // batch processing order (null: id order): the tracks in the order their
+    // photons are processed, and the exclusive scan of their counts in that
+    // order ([n_tracks + 1]); photon ids, hence results, do not change
+    const int32_t *order;
+    const uint64_t *order_off;
     double n_radiator;
     // explicit
     const float *ex_o, *ex_d, *ex_l;

@@ -157,7 +157,7 @@ void free_scene(rich_scene *s) {
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     void *ptrs[] = {s->d_nodes, s->d_tris, s->d_inst, s->d_caps, s->d_caps_static, s->d_segs, s->d_rects,
                     s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counter, s->d_partials,
-                    s->d_tally};
+                    s->d_tally, s->d_order};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(prev);

@@ -30,6 +30,8 @@ struct rich_scene {
     unsigned long long *d_tally = nullptr;     // fate-count slots shared by launches on this scene
     float *d_partials = nullptr;               // adjoint per-block partial sums
     size_t partials_floats = 0;
+    void *d_order = nullptr;                   // batch processing order (cells, tracks, offsets)
+    size_t order_bytes = 0;
 
     rich::DevScene dev{};
     std::vector<int32_t> mat_kind;             // host copy of the material kinds

@@ -162,8 +162,9 @@ __device__ __forceinline__ int find_track(const uint64_t *off, int n_tracks, uin
 
 // Track of photon g when the wave's photons mostly share one: a scalar
 // binary search (constant address space, wave-uniform index) for the wave's
-// first active photon, and the per-lane search only for lanes outside that
-// track's id range.
+// first active photon; lanes outside that track's id range try the next two
+// tracks (a wave of consecutive ids that crosses a boundary) and search on
+// their own only beyond them.
 __device__ __forceinline__ int find_track_wave(const uint64_t *off, int n_tracks, uint64_t g) {
     const RICH_CONST uint64_t *oc = (const RICH_CONST uint64_t *)off;
     const uint64_t g0 = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g >> 32)) << 32) |
@@ -174,6 +175,10 @@ __device__ __forceinline__ int find_track_wave(const uint64_t *off, int n_tracks
         if (oc[mid] <= g0) lo = mid; else hi = mid;
     }
     if (g >= oc[lo] && g < oc[lo + 1]) return lo;
+    if (g >= oc[lo + 1]) {
+        for (int k = lo + 1; k < lo + 3 && k < n_tracks; ++k)
+            if (g < off[k + 1]) return k;
+    }
     return find_track(off, n_tracks, g);
 }
 
@@ -188,9 +193,10 @@ __device__ __forceinline__ void basis(V3 n, V3 &b1, V3 &b2) {
 
 // wave_track: the wave's photons come from consecutive ids (forward and batch
 // kernels), so most lanes share the first lane's track; the adjoint's queued
-// photons do not, and search per lane.
+// photons do not, and search per lane.  track >= 0: the caller knows the
+// photon's track (batch processing order) and no search is made.
 __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t seed, uint64_t g, uint64_t i,
-                                              bool wave_track = true) {
+                                              bool wave_track = true, int track = -1) {
     uint4 w = photon_block(seed, g, 0);
     Photon ph;
     ph.u_qe = u24(w.w);
@@ -206,7 +212,9 @@ __device__ __forceinline__ Photon make_photon(const DevSource &src, uint64_t see
     V3 P0, T, E1, E2;
     float L, ct, st, beta;
     if (src.kind == 1) {
-        int k = wave_track ? find_track_wave(src.offsets, src.n_tracks, g) : find_track(src.offsets, src.n_tracks, g);
+        int k = track >= 0 ? track
+                           : (wave_track ? find_track_wave(src.offsets, src.n_tracks, g)
+                                         : find_track(src.offsets, src.n_tracks, g));
         const float4 *tr = reinterpret_cast<const float4 *>(src.tracks) + 2 * k;
         float4 a = tr[0], b = tr[1];
         P0 = V3{a.x, a.y, a.z};

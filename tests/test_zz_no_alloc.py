@@ -63,8 +63,10 @@ def test_noalloc_adjoint_matches_the_allocating_one(R):
 
 
 def test_noalloc_adjoint_refuses_what_does_not_fit(R):
-    """256 segments and 3e6 photons need 1465 x 1538 floats of partial sums, beyond the 2^21 the
-    array holds: RICH_ERANGE, nothing launched (outputs untouched); 1e5 photons fit and match."""
+    """2.5e9 photons with a mask need 7.3 MB of mask counts and offsets besides the partial sums of
+    256 segments: beyond the 8 MiB array, so RICH_ERANGE and nothing launched (outputs untouched).
+    The mask is all zeros and grad_uv one row: had anything run, it would read no photon's data.
+    1e5 photons fit and match rich_propagate_adjoint."""
     import torch
     cells = I.grid_cells(16, 16)
     scene = I.scene_g1()
@@ -73,17 +75,20 @@ def test_noalloc_adjoint_refuses_what_does_not_fit(R):
     scene["caps"] = I._caps_for_cells(cells, list(range(len(cells))))
     gs = R.Scene(scene)
     s, keep = R.make_source(I.point_source())
-    n = 3_000_000
-    tg = torch.zeros((n, 2), device="cuda")
+    n = 2_500_000_000
+    mask = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    gu = torch.zeros((1, 2), device="cuda")
     grad = torch.full((gs.n_segments, 6), 7.0, device="cuda")
     loss = torch.full((1,), 7.0, device="cuda")
+    print(f"no-alloc refusal: {n} photons, {gs.n_segments} segments", flush=True)
     with pytest.raises(R.RichError) as e:
-        R.rich_propagate_adjoint_noalloc(gs.handle, s, None, n, 1, 0, None, tg, None, None, grad, loss)
+        R.rich_propagate_adjoint_noalloc(gs.handle, s, None, n, 1, 0, gu, None, mask, None, grad, loss)
     assert e.value.code == R.RICH_ERANGE
     torch.cuda.synchronize()
     assert bool((grad == 7.0).all()) and float(loss[0]) == 7.0
+    del mask
     n = 100_000
-    tg = tg[:n].contiguous()
+    tg = torch.zeros((n, 2), device="cuda")
     for fn in (R.rich_propagate_adjoint_noalloc, R.rich_propagate_adjoint):
         fn(gs.handle, s, None, n, 1, 0, None, tg, None, None, grad, loss)
         torch.cuda.synchronize()
