@@ -477,25 +477,29 @@ __global__ __launch_bounds__(1024) void order_scan_cells_kernel(uint32_t *hist) 
 // Track t takes the next position of its cell (order within a cell is that of
 // the atomics: it does not change any photon's result), and position pos goes
 // to partition pos mod parts: order[] lists partition 0's tracks, then 1's, ...
-__global__ void order_scatter_kernel(const uint32_t *cell_of, uint32_t *cursor, int n_tracks, int parts,
-                                     int32_t *order) {
+// Each position's photon count goes beside it, into order_off (scanned next).
+__global__ void order_scatter_kernel(const uint32_t *cell_of, const uint64_t *offsets, uint32_t *cursor,
+                                     int n_tracks, int parts, int32_t *order, uint64_t *order_count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tracks) return;
     const uint32_t pos = atomicAdd(cursor + cell_of[t], 1u);
     const uint32_t c = pos % (uint32_t)parts, per = (uint32_t)n_tracks / (uint32_t)parts;
     const uint32_t rem = (uint32_t)n_tracks % (uint32_t)parts;
-    order[c * per + min(c, rem) + pos / (uint32_t)parts] = t;
+    const uint32_t q = c * per + min(c, rem) + pos / (uint32_t)parts;
+    order[q] = t;
+    order_count[q] = offsets[t + 1] - offsets[t];
 }
 
-// order_off[q] = photons of the tracks before position q (one block).
-__global__ __launch_bounds__(1024) void order_offsets_kernel(const int32_t *order, const uint64_t *offsets,
-                                                             int n_tracks, uint64_t *order_off) {
+// In place: photon counts by position -> photons of the tracks before each
+// position, order_off[n_tracks] = the total (one block).
+__global__ __launch_bounds__(1024) void order_offsets_kernel(int n_tracks, uint64_t *order_off) {
     __shared__ unsigned long long part[1024];
     const int t = threadIdx.x;
     const int per = (n_tracks + 1023) / 1024;
     const int lo = min(t * per, n_tracks), hi = min(lo + per, n_tracks);
     unsigned long long sum = 0;
-    for (int q = lo; q < hi; ++q) sum += offsets[order[q] + 1] - offsets[order[q]];
+#pragma unroll 8
+    for (int q = lo; q < hi; ++q) sum += order_off[q];   // unrolled: the loads overlap
     part[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -505,9 +509,11 @@ __global__ __launch_bounds__(1024) void order_offsets_kernel(const int32_t *orde
         __syncthreads();
     }
     unsigned long long run = part[t] - sum;
+#pragma unroll 8
     for (int q = lo; q < hi; ++q) {
+        const unsigned long long c = order_off[q];
         order_off[q] = run;
-        run += offsets[order[q] + 1] - offsets[order[q]];
+        run += c;
     }
     if (t == 1023) order_off[n_tracks] = part[1023];
 }
@@ -541,11 +547,10 @@ hipError_t launch_order(const DevSource &src, int n_parts, void *buffer, hipStre
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(order_scan_cells_kernel, dim3(1), dim3(1024), 0, st, hist);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)cell_of, hist, T,
-                       n_parts, order);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)cell_of, src.offsets,
+                       hist, T, n_parts, order, order_off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(1024), 0, st, (const int32_t *)order, src.offsets, T,
-                       order_off);
+    hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(1024), 0, st, T, order_off);
     return hipGetLastError();
 }
 
