@@ -337,14 +337,17 @@ __device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSour
 }
 
 constexpr int kSortGroup = 1024;   // photons regrouped together by cone azimuth
-constexpr int kSortBins = 128;
+constexpr int kSortBins = 128;     // a multiple of 64
+static_assert(kSortBins % 64 == 0 && kSortGroup % kForwardBlock == 0 && kSortGroup % 2 == 0 && kSortGroup <= 65536,
+              "regrouping shape");
 
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                                 uint64_t first, uint64_t seed) {
     extern __shared__ uint32_t lds_stack[];
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
-    uint32_t *perm = lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64);
-    uint32_t *bins = perm + kSortGroup;
+    // slot indices of the regrouped group (16 bits: kSortGroup <= 65536), then the bins
+    uint16_t *perm = reinterpret_cast<uint16_t *>(lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64));
+    uint32_t *bins = reinterpret_cast<uint32_t *>(perm + kSortGroup);
     const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
     if (!regroup) {
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
         constexpr int per = kSortGroup / kForwardBlock;
         const uint64_t stride = (uint64_t)gridDim.x * kSortGroup;
         for (uint64_t base = (uint64_t)blockIdx.x * kSortGroup; base < n; base += stride) {
-            if (threadIdx.x < kSortBins) bins[threadIdx.x] = 0;
+            for (int q = threadIdx.x; q < kSortBins; q += kForwardBlock) bins[q] = 0;
             __syncthreads();
             uint32_t bin[per], rank[per];
             for (int j = 0; j < per; ++j) {
@@ -373,19 +376,28 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
                 rank[j] = atomicAdd(bins + bin[j], 1u);
             }
             __syncthreads();
-            if (threadIdx.x < 64) {   // exclusive scan of the 128 bin counts by one wave
-                const uint32_t a = bins[2 * threadIdx.x], b = bins[2 * threadIdx.x + 1];
-                uint32_t incl = a + b;
+            if (threadIdx.x < 64) {   // exclusive scan of the bin counts by one wave, kSortBins / 64 per lane
+                constexpr int bpl = kSortBins / 64;
+                uint32_t c[bpl], sum = 0;
+#pragma unroll
+                for (int q = 0; q < bpl; ++q) {
+                    c[q] = bins[bpl * threadIdx.x + q];
+                    sum += c[q];
+                }
+                uint32_t incl = sum;
                 for (int d = 1; d < 64; d <<= 1) {
                     uint32_t v = __shfl_up(incl, d);
                     if ((int)threadIdx.x >= d) incl += v;
                 }
-                const uint32_t excl = incl - a - b;
-                bins[2 * threadIdx.x] = excl;
-                bins[2 * threadIdx.x + 1] = excl + a;
+                uint32_t run = incl - sum;
+#pragma unroll
+                for (int q = 0; q < bpl; ++q) {
+                    bins[bpl * threadIdx.x + q] = run;
+                    run += c[q];
+                }
             }
             __syncthreads();
-            for (int j = 0; j < per; ++j) perm[bins[bin[j]] + rank[j]] = (uint32_t)(j * kForwardBlock + threadIdx.x);
+            for (int j = 0; j < per; ++j) perm[bins[bin[j]] + rank[j]] = (uint16_t)(j * kForwardBlock + threadIdx.x);
             __syncthreads();
             for (int j = 0; j < per; ++j) {
                 const uint64_t i = base + perm[j * kForwardBlock + threadIdx.x];
@@ -407,7 +419,7 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
     uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
     if (blocks > cap) blocks = cap;
     size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + kFates * (kForwardBlock / 64) * sizeof(uint32_t) +
-                 (kSortGroup + kSortBins) * sizeof(uint32_t);
+                 kSortGroup * sizeof(uint16_t) + kSortBins * sizeof(uint32_t);
     hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
                        seed);
     return hipGetLastError();

@@ -104,6 +104,29 @@ def test_gradient_is_deterministic(R, c4small):
     assert np.array_equal(to_np(g1), to_np(g2)) and float(l1) == float(l2)
 
 
+def test_mask_forms_give_the_same_sums(R, c4small):
+    """The mask's count and scan read it with 16-byte loads when it is aligned, bytes otherwise: a
+    mask one byte into its buffer gives bit for bit the sums of the aligned one; a mask of all ones
+    gives those of no mask."""
+    import torch
+    p = c4small
+    gs = R.Scene(p["scene"])
+    tg = np.nan_to_num(p["target"]["hit_uv"])
+    mask = torch.as_tensor(p["mask"].astype(np.uint8), device="cuda")
+    g0, l0 = R.adjoint(gs, p["src"], p["seed"], targets=tg, mask=mask)
+    buf = torch.zeros(mask.numel() + 1, dtype=torch.uint8, device="cuda")
+    buf[1:] = mask
+    shifted = buf[1:]
+    assert shifted.data_ptr() % 16 != 0
+    g1, l1 = R.adjoint(gs, p["src"], p["seed"], targets=tg, mask=shifted)
+    assert np.array_equal(to_np(g0), to_np(g1)) and np.array_equal(to_np(l0), to_np(l1))
+    ones = torch.ones_like(mask)
+    g2, l2 = R.adjoint(gs, p["src"], p["seed"], targets=tg, mask=ones)
+    g3, l3 = R.adjoint(gs, p["src"], p["seed"], targets=tg, mask=None)
+    assert np.array_equal(to_np(g2), to_np(g3)) and np.array_equal(to_np(l2), to_np(l3))
+    assert gs.status() == 0
+
+
 def test_gpu_finite_differences_fp32(R, c4small):
     """Central differences of the GPU's own FP32 forward loss agree with its adjoint at 1e-2."""
     import torch

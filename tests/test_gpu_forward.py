@@ -505,6 +505,39 @@ def test_batch_size_other_than_the_track_total_is_flagged(R, orc):
     assert gs.status() == 0 and int(to_np(out["fate_counts"]).sum()) == n
 
 
+def test_batch_processing_order_with_empty_tracks(R, orc):
+    """Large batches on meshed scenes are processed in an order of the tracks by direction dealt to
+    the XCD partitions: with tracks of no photons among them (first, a run in the middle, last),
+    every photon still gets its own id, random numbers and results (2.4e6 photons: the order is on).
+    With n_photons one short of the total the order is off and the prefix is traced in id order."""
+    cfg = I.config(3)
+    rng = np.random.default_rng(33)
+    tracks = I.sample_tracks(rng, 600)
+    counts = rng.integers(1000, 7000, size=600)
+    counts[[0, 100, 101, 102, 599]] = 0
+    src = I.batch_source(tracks, counts)
+    n = int(counts.sum())
+    assert n >= 1 << 21
+    gs = R.Scene(cfg["scene"])
+    ids = np.arange(0, n, 97, dtype=np.uint64)
+    ref = orc.propagate(cfg["scene"], src, 0, cfg["seed"], ids=ids)
+    for tune in (R.tuning(256, 256, 4), R.tuning(512, 1024, 1)):
+        print(f"ordered batch {tune.block}x{tune.chunk}x{tune.blocks_per_cu}: {n} photons", flush=True)
+        out = R.propagate_batch(gs, src, cfg["seed"], tune=tune)
+        sub = {k: to_np(out[k])[ids.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+        compare(sub, ref, label=f"ordered batch {tune.block}x{tune.chunk}")
+        _hist_counts_consistent(out, gs.nx, gs.ny)
+        assert gs.status() == 0
+    b, keep, nb = R.make_batch(src)
+    t, o = R.alloc_outputs(gs, n - 1)
+    R.rich_propagate_batch(gs.handle, b, n - 1, cfg["seed"], o, R.tuning(256, 256, 4))
+    assert gs.status() == R.FLAG_BATCH_SIZE
+    pre = ids[ids < n - 1]
+    sub = {k: to_np(t[k])[pre.astype(np.int64)] for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    refp = {k: v[: len(pre)] for k, v in ref.items()}
+    compare(sub, refp, label="batch prefix, order off")
+
+
 def test_hit_list_with_regrouped_photons(R, c2):
     """The compact hit list when photons are traced out of id order (regrouped by azimuth), from the
     forward kernel on the meshed scene and from the persistent batch kernel: exactly the DETECTED
