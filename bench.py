@@ -52,8 +52,9 @@ ACTIVE_LANE_OPS_PER_PHOTON = 5067.6
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
-# KiB per dispatch, scaled by the 256 MiB copy-kernel calibration, / 1e7 photons.
-TRAFFIC_BYTES_PER_PHOTON = (1064.52 * 1.9998 + 1177078.5) * 1024 / 1e7
+# KiB per dispatch, scaled by the 256 MiB copy-kernel calibration (262,144 KiB copied: FETCH_SIZE
+# reads 131,086, WRITE_SIZE 262,144), / 1e7 photons (profiles/forward_kernel_c2_counters.md).
+TRAFFIC_BYTES_PER_PHOTON = (1072.7 * 1.9998 + 1181110.0) * 1024 / 1e7
 
 
 def parse():
@@ -63,7 +64,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-forms", action="store_true", help="only the headline workload")
-    p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large,largefit", help="comma list of extra forms")
+    p.add_argument("--forms", default="c1,batched,adjoint,fit,prefilter,large,largefit", help="comma list of extra forms (also: sizes)")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     p.add_argument("--fixed-tuning", action="store_true",
                    help="batch forms use block 256, chunk 256, 4 blocks per CU instead of the autotuner "
@@ -238,6 +239,30 @@ def form_align_fit(R, I, stream, steps, k=4):
     return out
 
 
+def form_scene_sizes(R, I, stream, steps):
+    """The large scene's batch forward against its triangle count: the same 8192 tracks (2442
+    photons each, 2.0e7) on the 32-segment mirror meshed at 137x228, 68x114 and 34x57 quads per
+    segment.  Not in the default forms (it builds three scenes)."""
+    import numpy as np
+    cfg = I.config(5)
+    src = I.batch_source(cfg["source"]["tracks"], np.full(len(cfg["source"]["tracks"]), 2442))
+    rows = []
+    for quads in ((137, 228), (68, 114), (34, 57)):
+        sc = R.Scene(I.scene_g5(seg_quads=quads))
+        info = sc.info()
+        b, keep, n = R.make_batch(src)
+        t, o = R.alloc_outputs(sc, n)
+        tune = R.rich_autotune(sc.handle, b, n, cfg["seed"])
+        ms = time_steps(lambda: R.rich_propagate_batch(sc.handle, b, n, cfg["seed"], o, tune, stream), steps, 2,
+                        stream)
+        assert sc.status() == 0
+        rows.append({"segment_quads": list(quads), "triangles": info["n_triangles"], "bvh_nodes": info["n_nodes"],
+                     "device_mb": round(info["device_bytes"] / 1e6, 1), "ms_per_step": ms,
+                     "photons_per_s": n / (ms * 1e-3)})
+        del t, o, sc
+    return {"workload": "large scene at three mesh resolutions, 2.0e7 photons", "rows": rows}
+
+
 def form_prefilter(R, I, stream, steps):
     """The headline workload with the accept-reject of QE x R x R before propagation."""
     cfg = I.config(2)
@@ -356,6 +381,8 @@ def main():
             forms["fwd_adjoint"] = _fwd_adjoint(R, I, I.config(4), stream, half, args.fixed_tuning)
         if "fit" in want:
             forms["align_fit"] = form_align_fit(R, I, stream, 300)
+        if "sizes" in want:
+            forms["scene_sizes"] = form_scene_sizes(R, I, stream, 5)
         if "largefit" in want:
             forms["large_align_fit"] = form_align_fit(R, I, stream, 300, k=5)
         if "prefilter" in want:
