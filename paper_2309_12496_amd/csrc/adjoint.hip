@@ -507,9 +507,14 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(3))) 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 64 * q + lane;
-                id[q] = j < cnt ? cell(j) : 0u;
-                bin[q] = j < cnt ? (photon_block(seed, first + id[q], 0).x >> 26) : 64u;
-                if (j < cnt) atomicAdd(&cell(512 + (int)bin[q]), 1u);
+                id[q] = 0u;
+                bin[q] = 64u;
+                if (j < cnt) {
+                    id[q] = cell(j);
+                    work(kWorkSortKeys);
+                    bin[q] = photon_block(seed, first + id[q], 0).x >> 26;
+                    atomicAdd(&cell(512 + (int)bin[q]), 1u);
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             const uint32_t nb = cell(512 + lane);

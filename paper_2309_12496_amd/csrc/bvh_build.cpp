@@ -14,7 +14,12 @@ namespace rich {
 namespace {
 
 constexpr int kBins = 32;
-constexpr uint32_t kLeafSize = 4;
+constexpr uint32_t kLeafSize = 4;      // largest leaf
+constexpr uint32_t kAlwaysLeaf = 1;    // nodes of this many triangles or fewer are leaves
+// Surface-area cost of testing a node against that of one triangle: a range
+// of up to kLeafSize triangles becomes a leaf when testing them all costs no
+// more than the node plus the children the split would make.
+constexpr double kNodeCost = 1.0;
 
 struct BNode {
     BuildBox box;
@@ -136,7 +141,7 @@ struct Builder {
         bn[me].box = box;
         bn[me].first = first;
         bn[me].count = count;
-        if (count <= kLeafSize) return me;
+        if (count <= kAlwaysLeaf) return me;
 
         // binned SAH over the centroid bounds
         double best_cost = std::numeric_limits<double>::infinity();
@@ -177,6 +182,7 @@ struct Builder {
                 }
             }
         }
+        if (count <= kLeafSize && (best_axis < 0 || area(box) * count <= kNodeCost * area(box) + best_cost)) return me;
         uint32_t mid;
         if (best_axis >= 0) {
             double ext = cb.hi[best_axis] - cb.lo[best_axis];
