@@ -290,9 +290,9 @@ __device__ __forceinline__ void adjoint_pass(const DevScene &S, const DevSource 
         o0 = ph.o;
         d0 = ph.d;
         if (!src.prefilter) {
-            propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec);
+            propagate(S, det, ph, seed, g, stk, end, rec);
         } else if (prefilter_keep(S, det, src, ph, seed, g)) {
-            propagate(S, det, ph, seed, g, stk, blockDim.x, end, rec, false);
+            propagate(S, det, ph, seed, g, stk, end, rec, false);
         } else {
             end.fate = kPrefiltered;
         }
@@ -422,15 +422,15 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(3))) 
     const int wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
     const int width = a.n_par + 2;
-    uint32_t *stk = lds + threadIdx.x;
+    uint32_t *stk = lane_stack(lds);
     float *acc_all = reinterpret_cast<float *>(lds + (size_t)blockDim.x * kStackDepth);
     float *acc = acc_all + wave * width;
     for (int j = lane; j < width; j += 64) acc[j] = 0.0f;
     // While no photon is traced the wave's own stack columns hold its group:
     // rows 0-3 the ids in rank order, rows 4-7 the regrouped ids, row 8 the
     // running offsets of the 64 azimuth bins.
-    const int stride = blockDim.x;
-    auto cell = [&](int j) -> uint32_t & { return lds[(j >> 6) * stride + 64 * wave + (j & 63)]; };
+    uint32_t *const wave_rows = lds + wave * (kStackDepth * kStackRow);
+    auto cell = [&](int j) -> uint32_t & { return wave_rows[j]; };
 
     const RICH_CONST DetDev &det = cref(*S.det);
     // Squared residual cut; a negative or NaN cut admits no photon.

@@ -207,7 +207,7 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
 // VGPRs, spills the extra scalar state and reads the detector per lane.
 template <bool kConstDet>
 __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
-                                          uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk, int stride,
+                                          uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk,
                                           int track = -1) {
     PathEnd end;
     end.fate = -1;
@@ -217,9 +217,9 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
         NoRecord rec;
         auto run = [&](const auto &det) {
             if (!src.prefilter) {
-                propagate(S, det, ph, seed, g, stk, stride, end, rec);
+                propagate(S, det, ph, seed, g, stk, end, rec);
             } else if (prefilter_keep(S, det, src, ph, seed, g)) {
-                propagate(S, det, ph, seed, g, stk, stride, end, rec, false);
+                propagate(S, det, ph, seed, g, stk, end, rec, false);
             } else {
                 end.fate = kPrefiltered;
             }
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
             uint64_t i = base + threadIdx.x;
-            int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+            int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lane_stack(lds_stack));
             if (out.fate_counts) tally_wave(cnt, fate);
         }
     } else {
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
             __syncthreads();
             for (int j = 0; j < per; ++j) {
                 const uint64_t i = base + perm[j * kForwardBlock + threadIdx.x];
-                int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lds_stack + threadIdx.x, blockDim.x);
+                int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lane_stack(lds_stack));
                 if (out.fate_counts) tally_wave(cnt, fate);
             }
             __syncthreads();
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
     int whole_batch, uint64_t part, int n_parts) {
     extern __shared__ uint32_t lds_stack[];
     const int lane = __lane_id();
-    uint32_t *stk = lds_stack + threadIdx.x;
+    uint32_t *stk = lane_stack(lds_stack);
     const int wave = threadIdx.x >> 6;
     uint32_t *wperm = lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64) +
                       (size_t)wave * (kWaveGroup + 64);
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void b
                 const uint64_t v = base + (uint64_t)k + off;
                 int tk = -1;
                 const uint64_t g = v < n ? batch_photon_id(src, v, n, tk) : v;
-                int fate = photon_job<false>(S, src, out, v < n, g, g, seed, stk, blockDim.x, tk);
+                int fate = photon_job<false>(S, src, out, v < n, g, g, seed, stk, tk);
                 if (out.fate_counts) tally_wave(cnt, fate);
             }
             if (regroup) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

@@ -16,6 +16,10 @@ namespace rich {
 
 constexpr uint32_t kStreamTag = 0x52494348u;   // fourth Philox counter word ("RICH")
 constexpr int kStackDepth = 32;                // per-lane traversal stack entries (LDS)
+// A wave's stacks are kStackDepth rows of 64 words in LDS: lane l's entry d
+// is word 64 d + l of its wave's block.  The lanes of a row sit in distinct
+// banks at any mix of depths, and consecutive entries are a fixed 256 B apart.
+constexpr int kStackRow = 64;
 constexpr int kMaxTable = 32;
 constexpr int kFates = 7;                      // photon fates, RICH_N_FATES
 constexpr int kTallySlots = 16;                // fate-count slots, one 128-byte line each

@@ -447,14 +447,21 @@ __device__ __forceinline__ void set_origin(Ray &r, V3 o) {
     r.oi = V3{o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z};
 }
 
+// This lane's traversal stack in a block's LDS (layout at kStackRow).
+__device__ __forceinline__ uint32_t *lane_stack(uint32_t *lds) {
+    return lds + (threadIdx.x >> 6) * (kStackDepth * kStackRow) + (threadIdx.x & 63);
+}
+
 // Closest triangle along (ow, dw) with t < h.t, through the two-level BVH4.
-// stk points at this lane's first LDS stack slot; entries are `stride` apart.
-__device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hit &h, uint32_t *stk, int stride) {
+// stk is this lane's stack (lane_stack); sp is the word offset of its next
+// free entry, depth x kStackRow.
+__device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hit &h, uint32_t *stk) {
     const V3 ow = world.o, dw = world.d;
     Ray r = world;
     int inst = -1;
     bool moved = false;   // current frame rotated/scaled (a parametrised segment)
     int sp = 0;
+    constexpr int kEnd = kStackDepth * kStackRow;
     uint32_t ref = S.top_root;
     const float tmin = S.t_min;
     while (true) {
@@ -488,22 +495,35 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             const uint32_t kMiss = 0x7F800000u;   // +inf
             if (k0 >= kMiss) {
                 if (sp == 0) break;
-                ref = stk[(--sp) * stride];
+                sp -= kStackRow;
+                ref = stk[sp];
                 continue;
             }
-            // children of empty slots never pass the slab test (inverted boxes)
+            // child of a key by its slot bits, with selects only (children of
+            // empty slots never pass the slab test: their boxes are inverted)
             auto pick = [&](uint32_t k) -> uint32_t {
-                uint32_t j = k & 3u;
-                return j == 0 ? ch.x : (j == 1 ? ch.y : (j == 2 ? ch.z : ch.w));
+                const uint32_t lo = (k & 1u) ? ch.y : ch.x;
+                const uint32_t hi = (k & 1u) ? ch.w : ch.z;
+                return (k & 2u) ? hi : lo;
             };
-            int need = (k1 < kMiss) + (k2 < kMiss) + (k3 < kMiss);
-            if (sp + need > kStackDepth) {
-                atomicOr(S.status, 2u);  // RICH_FLAG_STACK_OVERFLOW
-                need = kStackDepth - sp;
+            // the hit children after the nearest go on the stack, farthest
+            // deepest; the keys are sorted, so k3 hit implies k2 and k1 hit
+            uint32_t p2 = k2 < kMiss, p3 = k3 < kMiss;
+            int need = (k1 < kMiss) + (int)p2 + (int)p3;
+            if (sp + need * kStackRow > kEnd) {
+                atomicOr(S.status, 2u);  // RICH_FLAG_STACK_OVERFLOW: the farthest are dropped
+                need = (kEnd - sp) / kStackRow;
+                p3 = need >= 3;
+                p2 = need >= 2;
             }
-            if (need >= 3) stk[(sp++) * stride] = pick(k3);
-            if (need >= 2) stk[(sp++) * stride] = pick(k2);
-            if (need >= 1) stk[(sp++) * stride] = pick(k1);
+            if (need > 0) {
+                // the entries land in slots 0..need-1 above the top: a write to
+                // a slot that a later write also takes is overwritten by it
+                stk[sp] = pick(k3);
+                stk[sp + (int)p3 * kStackRow] = pick(k2);
+                stk[sp + (int)(p2 + p3) * kStackRow] = pick(k1);
+                sp += need * kStackRow;
+            }
             ref = pick(k0);
             continue;
         }
@@ -514,10 +534,11 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             moved = false;
         } else if (ref & kInstBit) {
             int k = (int)(ref & ~(kLeafBit | kInstBit));
-            if (sp + 1 > kStackDepth) {
+            if (sp == kEnd) {
                 atomicOr(S.status, 2u);
             } else {
-                stk[(sp++) * stride] = kExitMarker;
+                stk[sp] = kExitMarker;
+                sp += kStackRow;
                 work(kWorkInstances);
                 const Instance &in = S.inst[k];
                 if (in.segment < 0) {
@@ -555,13 +576,13 @@ __device__ __forceinline__ void traverse(const DevScene &S, const Ray &world, Hi
             }
         }
         if (sp == 0) break;
-        ref = stk[(--sp) * stride];
+        sp -= kStackRow;
+        ref = stk[sp];
     }
 }
 
 template <class D>
-__device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 o, V3 d, Hit &h, uint32_t *stk,
-                                            int stride) {
+__device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 o, V3 d, Hit &h, uint32_t *stk) {
     h.t = INFINITY;
     h.prim = 0xFFFFFFFFu;
     h.tri = 0;
@@ -602,7 +623,7 @@ __device__ __forceinline__ void closest_hit(const DevScene &S, const D &det, V3 
         h.t = t;
         h.prim = S.prim_box;
     }
-    if (S.has_mesh) traverse(S, r, h, stk, stride);
+    if (S.has_mesh) traverse(S, r, h, stk);
 }
 
 // Reflectivity of material `mat` at `lambda`.  The loop over materials is
@@ -670,7 +691,7 @@ __device__ __forceinline__ bool prefilter_keep(const DevScene &S, const D &det, 
 // pre-filter) mirrors always reflect and the detector always detects.
 template <class D, class Rec>
 __device__ __forceinline__ void propagate(const DevScene &S, const D &det, const Photon &ph, uint64_t seed,
-                                          uint64_t g, uint32_t *stk, int stride, PathEnd &end, Rec &rec,
+                                          uint64_t g, uint32_t *stk, PathEnd &end, Rec &rec,
                                           bool efficiencies = true) {
     V3 o = ph.o, d = ph.d;
     end.fate = kMaxBounces;
@@ -687,7 +708,7 @@ __device__ __forceinline__ void propagate(const DevScene &S, const D &det, const
     for (int b = 0; b < S.max_bounces; ++b) {
         Hit h;
         work(kWorkQueries);
-        closest_hit(S, det, o, d, h, stk, stride);
+        closest_hit(S, det, o, d, h, stk);
         if (h.prim == 0xFFFFFFFFu) {
             end.fate = kEscaped;
             break;
