@@ -77,32 +77,37 @@ struct Builder {
         }
     }
 
+    // Given groups: an instance that holds several meshes gets one subtree per
+    // group (a plane of a planar mesh, or a whole curved mesh), so that the
+    // SAH never mixes a thin enclosure wall into a mirror's boxes.  Returns the
+    // root, or -1 unless every triangle has a group and there are two or more.
+    int build_grouped() {
+        std::vector<int> grp(tris.size());
+        std::map<int, int> dense;
+        for (size_t i = 0; i < tris.size(); ++i) {
+            if (tris[i].group < 0) return -1;
+            grp[i] = dense.emplace(tris[i].group, (int)dense.size()).first->second;
+        }
+        if (dense.size() < 2) return -1;
+        return chain_groups(grp, (int)dense.size());
+    }
+
     // Planar grouping: a mesh made of a few planes (an enclosure's walls) gets
     // one subtree per plane, the planes chained under the root so that the
     // BVH4 root holds thin per-wall boxes rather than half-box boxes that
     // contain every ray starting inside.  Returns the root, or -1 if the mesh
     // is not a union of 2..64 planes.
     int build_planar() {
-        size_t n = tris.size();
-        std::map<std::tuple<long long, long long, long long, long long>, int> key_to_group;
-        std::vector<int> grp(n);
-        for (size_t i = 0; i < n; ++i) {
-            const BuildTri &t = tris[i];
-            double off = t.n[0] * t.v[0][0] + t.n[1] * t.v[0][1] + t.n[2] * t.v[0][2];
-            auto key = std::make_tuple(std::llround(t.n[0] * 1e6), std::llround(t.n[1] * 1e6), std::llround(t.n[2] * 1e6),
-                                       std::llround(off * 1e3));
-            auto it = key_to_group.find(key);
-            if (it == key_to_group.end()) {
-                if (key_to_group.size() >= 64) return -1;
-                it = key_to_group.emplace(key, (int)key_to_group.size()).first;
-            }
-            grp[i] = it->second;
-        }
-        int ng = (int)key_to_group.size();
+        std::vector<int> grp;
+        int ng = plane_groups(tris, 64, grp);
         if (ng < 2) return -1;
+        return chain_groups(grp, ng);
+    }
+
+    // Subtrees of the groups, largest first, chained under the root.
+    int chain_groups(const std::vector<int> &grp, int ng) {
         std::vector<uint32_t> gcount(ng, 0);
         for (int g : grp) ++gcount[g];
-        // groups by decreasing size, triangles contiguous per group
         std::vector<int> order(ng);
         for (int g = 0; g < ng; ++g) order[g] = g;
         std::sort(order.begin(), order.end(), [&](int a, int b) { return gcount[a] > gcount[b] || (gcount[a] == gcount[b] && a < b); });
@@ -295,6 +300,29 @@ struct Emitter {
 
 }  // namespace
 
+bool PlaneKey::operator<(const PlaneKey &o) const {
+    return std::tie(nx, ny, nz, off) < std::tie(o.nx, o.ny, o.nz, o.off);
+}
+
+PlaneKey plane_key(const BuildTri &t) {
+    double off = t.n[0] * t.v[0][0] + t.n[1] * t.v[0][1] + t.n[2] * t.v[0][2];
+    return {std::llround(t.n[0] * 1e6), std::llround(t.n[1] * 1e6), std::llround(t.n[2] * 1e6), std::llround(off * 1e3)};
+}
+
+int plane_groups(const std::vector<BuildTri> &tris, int max_groups, std::vector<int> &grp) {
+    std::map<PlaneKey, int> key_to_group;
+    grp.resize(tris.size());
+    for (size_t i = 0; i < tris.size(); ++i) {
+        auto it = key_to_group.find(plane_key(tris[i]));
+        if (it == key_to_group.end()) {
+            if ((int)key_to_group.size() >= max_groups) return -1;
+            it = key_to_group.emplace(plane_key(tris[i]), (int)key_to_group.size()).first;
+        }
+        grp[i] = it->second;
+    }
+    return (int)key_to_group.size();
+}
+
 float lower_f32(double x) {
     double pad = 1e-3 + 1e-6 * std::fabs(x);
     float f = (float)(x - pad);
@@ -313,7 +341,8 @@ uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes,
                          BuildBox *bounds) {
     Builder b(tris);
     b.bn.reserve(2 * tris.size() / kLeafSize + 2);
-    int top = b.build_planar();
+    int top = b.build_grouped();
+    if (top < 0) top = b.build_planar();
     if (top < 0) top = b.build(0, (uint32_t)tris.size());
     if (bounds) *bounds = b.bn[top].box;
     Emitter e{b.bn, b.idx, tris, nodes, out};

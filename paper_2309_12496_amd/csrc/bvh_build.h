@@ -13,6 +13,7 @@ struct BuildTri {
     double n[3];         // unit normal of the active side, computed in FP64
     uint32_t index;      // global triangle index (primitive order of the scene)
     uint32_t material;
+    int32_t group = -1;  // subtree of an instance that holds several meshes (-1: none)
 };
 
 struct BuildBox {
@@ -21,9 +22,22 @@ struct BuildBox {
 
 // Build a BVH4 over `tris`, appending nodes to `nodes` and leaf-ordered
 // triangles to `out`.  Returns the root node index; `depth` gets the number of
-// BVH4 levels and `bounds` the AABB of all triangles.
+// BVH4 levels and `bounds` the AABB of all triangles.  Triangles that all
+// carry a group (two or more groups) get one subtree per group.
 uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes, std::vector<Tri> &out, int *depth,
                          BuildBox *bounds);
+
+// Plane of a triangle as integers: unit normal to 1e-6, plane offset to 1e-3 mm.
+struct PlaneKey {
+    long long nx, ny, nz, off;
+    bool operator<(const PlaneKey &o) const;
+};
+PlaneKey plane_key(const BuildTri &t);
+
+// Plane of each triangle: triangles with equal plane keys share a group.
+// Groups are numbered in order of first appearance.  Returns the number of
+// groups, or -1 once a mesh has more than `max_groups` planes.
+int plane_groups(const std::vector<BuildTri> &tris, int max_groups, std::vector<int> &grp);
 
 // Build the top-level BVH4 over instance boxes; leaves reference instances.
 // The nodes are appended to `nodes` starting at the current size.

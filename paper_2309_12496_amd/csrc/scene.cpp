@@ -10,6 +10,7 @@
 #include <thread>
 #include <atomic>
 #include <algorithm>
+#include <map>
 
 #include "bvh_build.h"
 #include "kernels.h"
@@ -32,7 +33,7 @@ const char *last_error() { return g_last_error.c_str(); }
 
 namespace {
 
-constexpr int64_t kSmallMesh = 1000;   // static meshes below this share one instance
+constexpr int kMaxMeshPlanes = 64;     // a fixed mesh of at most this many planes is grouped by plane
 
 bool finite3(const double *p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
@@ -191,7 +192,13 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     // --- group meshes into instances
     std::vector<InstanceBuild> inst;
     std::vector<int> seg_inst(d->n_segments, -1);
-    int small_inst = -1;
+    int static_inst = -1;
+    // Every fixed mesh goes into one instance.  Its BVH gets a subtree per
+    // group: per plane for a mesh made of a few planes (planes shared by
+    // several meshes, like tiles of one flat mirror, form one group), and per
+    // mesh for the others.
+    std::map<PlaneKey, int> plane_group;
+    int n_groups = 0;
     uint32_t tri_index = 0;
     for (int i = 0; i < d->n_meshes; ++i) {
         const rich_mesh &m = d->meshes[i];
@@ -204,16 +211,15 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
                 inst.back().segment = m.segment;
             }
             k = seg_inst[m.segment];
-        } else if (m.n_tri < kSmallMesh) {
-            if (small_inst < 0) {
-                small_inst = (int)inst.size();
+        } else {
+            if (static_inst < 0) {
+                static_inst = (int)inst.size();
                 inst.emplace_back();
             }
-            k = small_inst;
-        } else {
-            k = (int)inst.size();
-            inst.emplace_back();
+            k = static_inst;
         }
+        std::vector<BuildTri> mt;
+        mt.reserve((size_t)m.n_tri);
         for (int64_t q = 0; q < m.n_tri; ++q) {
             BuildTri t;
             const double *v = m.vertices + 9 * q;
@@ -226,8 +232,21 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
             for (int a = 0; a < 3; ++a) t.n[a] = len > 0 ? n[a] / len : 0.0;
             t.index = tri_index++;
             t.material = (uint32_t)m.material;
-            inst[k].tris.push_back(t);
+            mt.push_back(t);
         }
+        if (m.segment < 0) {
+            std::vector<int> grp;
+            if (plane_groups(mt, kMaxMeshPlanes, grp) > 0) {
+                for (auto &t : mt) {
+                    t.group = plane_group.emplace(plane_key(t), n_groups).first->second;
+                    if (t.group == n_groups) ++n_groups;
+                }
+            } else {
+                for (auto &t : mt) t.group = n_groups;
+                ++n_groups;
+            }
+        }
+        inst[k].tris.insert(inst[k].tris.end(), mt.begin(), mt.end());
     }
     // local frames: segment instances around the pivot, fixed ones around their box centre
     for (auto &in : inst) {
@@ -452,7 +471,8 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     S.n_inst = (int32_t)inst.size();
     S.has_mesh = inst.empty() ? 0 : 1;
     S.has_box = d->has_box ? 1 : 0;
-    S.top_root = 0;
+    // a scene of one instance starts in it: the top-level node would only hold its box
+    S.top_root = inst.size() == 1 ? make_inst(0) : 0;
     S.max_bounces = d->max_bounces;
     S.t_min = (float)d->t_min;
     S.prim_det = (uint32_t)(d->n_caps + d->n_rects);
