@@ -37,24 +37,24 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 # Algorithmic VALU work per photon of the headline workload, in 32-bit lane
 # operations: the method's units of work per photon counted on the GPU by the
-# measurement build (27.04 BVH4 nodes, 7.43 triangle tests, 3.72 leaves,
-# 6.48 instance entries, 2.78 closest-hit queries, 1.78 reflections, 0.85
+# measurement build (26.19 BVH4 nodes, 7.43 triangle tests, 3.72 leaves,
+# 2.78 instance entries, 2.78 closest-hit queries, 1.78 reflections, 0.85
 # detector hits, 2 Philox blocks) times the operations each takes
 # (paper_2309_12496_amd/work_counts.py; profiles/work_counts.md).
-ALU_OPS_PER_PHOTON = 3371.3
+ALU_OPS_PER_PHOTON = 3252.1
 # What forward_kernel executes per photon on the same workload (rocprofv3,
 # profiles/forward_kernel_c2_counters.md): SQ_INSTS_VALU x 64 / photons =
 # issued lane slots (inactive lanes of divergent waves included), and
 # SQ_THREAD_CYCLES_VALU / photons = lane operations of active lanes (the
 # counter reads 64 per instruction on a plain copy kernel).
-ISSUED_SLOTS_PER_PHOTON = 6763.2
-ACTIVE_LANE_OPS_PER_PHOTON = 4999.2
+ISSUED_SLOTS_PER_PHOTON = 6225.6
+ACTIVE_LANE_OPS_PER_PHOTON = 4601.2
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
 # KiB per dispatch, scaled by the 256 MiB copy-kernel calibration (262,144 KiB copied: FETCH_SIZE
 # reads 131,086, WRITE_SIZE 262,144), / 1e7 photons (profiles/forward_kernel_c2_counters.md).
-TRAFFIC_BYTES_PER_PHOTON = (1083.8 * 1.9998 + 1175390.0) * 1024 / 1e7
+TRAFFIC_BYTES_PER_PHOTON = (1116.7 * 1.9998 + 1134697.0) * 1024 / 1e7
 
 
 def parse():
@@ -358,7 +358,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"] + " (meshed RICH, 210,082 triangles, point emitter)",
                    "photons_per_step": n, "triangles": info["n_triangles"], "form": "forward",
-                   "scene_build_s": round(build_s, 3)},
+                   "scene_build_s": round(build_s, 3), "scene_build_host_s": round(info["build_seconds"], 3)},
         "roofline": roof,
         # the paper's own rates: wall-clock of whole Mitsuba calls (parse, JIT, render) on its workload
         "paper_reference": {"per_cpu_thread": {"value": 2e5, "unit": "photons/s",

@@ -4,9 +4,11 @@
 #include "bvh_build.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <limits>
 #include <map>
+#include <thread>
 #include <tuple>
 
 namespace rich {
@@ -116,15 +118,40 @@ struct Builder {
         std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return rank[grp[a]] < rank[grp[b]]; });
         std::vector<uint32_t> start(ng + 1, 0);
         for (int r = 0; r < ng; ++r) start[r + 1] = start[r] + gcount[order[r]];
-        return chain(0, ng, start);
+        // the groups' subtrees are independent: built on host threads into
+        // their own node lists, then appended in group order with their
+        // indices rebased (the same tree as building them in turn)
+        std::vector<std::vector<BNode>> local(ng);
+        std::vector<int> root(ng);
+        std::atomic<int> next{0};
+        auto work = [&]() {
+            for (int r; (r = next.fetch_add(1)) < ng;) root[r] = build_into(local[r], start[r], start[r + 1] - start[r]);
+        };
+        const int n_threads = (int)std::min<unsigned>({(unsigned)ng, std::max(1u, std::thread::hardware_concurrency()), 16u});
+        std::vector<std::thread> pool;
+        for (int i = 1; i < n_threads; ++i) pool.emplace_back(work);
+        work();
+        for (auto &th : pool) th.join();
+        for (int r = 0; r < ng; ++r) {
+            const int base = (int)bn.size();
+            for (BNode b : local[r]) {
+                if (b.left >= 0) {
+                    b.left += base;
+                    b.right += base;
+                }
+                bn.push_back(b);
+            }
+            root[r] += base;
+        }
+        return chain(0, ng, start, root);
     }
 
-    int chain(int r, int ng, const std::vector<uint32_t> &start) {
-        if (r == ng - 1) return build(start[r], start[r + 1] - start[r]);
+    int chain(int r, int ng, const std::vector<uint32_t> &start, const std::vector<int> &root) {
+        if (r == ng - 1) return root[r];
         int me = (int)bn.size();
         bn.emplace_back();
-        int l = build(start[r], start[r + 1] - start[r]);
-        int rt = chain(r + 1, ng, start);
+        int l = root[r];
+        int rt = chain(r + 1, ng, start, root);
         BuildBox box = bn[l].box;
         grow(box, bn[rt].box);
         bn[me].box = box;
@@ -135,17 +162,21 @@ struct Builder {
         return me;
     }
 
-    int build(uint32_t first, uint32_t count) {
-        int me = (int)bn.size();
-        bn.emplace_back();
+    int build(uint32_t first, uint32_t count) { return build_into(bn, first, count); }
+
+    // Binary SAH subtree over idx[first, first + count), appended to `out`
+    // (child indices are positions in `out`).
+    int build_into(std::vector<BNode> &out, uint32_t first, uint32_t count) {
+        int me = (int)out.size();
+        out.emplace_back();
         BuildBox box = empty_box(), cb = empty_box();
         for (uint32_t q = first; q < first + count; ++q) {
             grow(box, tbox[idx[q]]);
             grow(cb, &cen[3 * idx[q]]);
         }
-        bn[me].box = box;
-        bn[me].first = first;
-        bn[me].count = count;
+        out[me].box = box;
+        out[me].first = first;
+        out[me].count = count;
         if (count <= kAlwaysLeaf) return me;
 
         // binned SAH over the centroid bounds
@@ -201,10 +232,10 @@ struct Builder {
             mid = first + count / 2;  // all centroids coincide: split the index range
         }
         if (mid == first || mid == first + count) mid = first + count / 2;
-        int l = build(first, mid - first);
-        int r = build(mid, first + count - mid);
-        bn[me].left = l;
-        bn[me].right = r;
+        int l = build_into(out, first, mid - first);
+        int r = build_into(out, mid, first + count - mid);
+        out[me].left = l;
+        out[me].right = r;
         return me;
     }
 };
@@ -262,7 +293,10 @@ struct Emitter {
     std::vector<Tri> &out;
     int max_depth = 0;
 
+    bool bad_leaf = false;   // a leaf the reference encoding cannot hold
+
     uint32_t leaf_ref(const BNode &b) {
+        if (b.count == 0 || b.count > kLeafMaxTris) bad_leaf = true;
         uint32_t first = (uint32_t)out.size();
         for (uint32_t q = b.first; q < b.first + b.count; ++q) {
             const BuildTri &t = tris[idx[q]];
@@ -348,7 +382,7 @@ uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes,
     Emitter e{b.bn, b.idx, tris, nodes, out};
     uint32_t root = e.emit(top, 1);
     if (depth) *depth = e.max_depth;
-    return root;
+    return e.bad_leaf ? kEmpty : root;
 }
 
 uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &nodes, int *depth) {

@@ -23,7 +23,9 @@ struct BuildBox {
 // Build a BVH4 over `tris`, appending nodes to `nodes` and leaf-ordered
 // triangles to `out`.  Returns the root node index; `depth` gets the number of
 // BVH4 levels and `bounds` the AABB of all triangles.  Triangles that all
-// carry a group (two or more groups) get one subtree per group.
+// carry a group (two or more groups) get one subtree per group.  Returns
+// kEmpty if a leaf came out empty or larger than kLeafMaxTris (a builder
+// fault: the tree must not be used).
 uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes, std::vector<Tri> &out, int *depth,
                          BuildBox *bounds);
 

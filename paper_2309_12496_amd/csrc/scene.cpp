@@ -295,6 +295,14 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
         for (auto &th : pool) th.join();
     }
     for (size_t k = 0; k < inst.size(); ++k) {
+        if (roots[k] == kEmpty) {
+            free_scene(s);
+            (void)hipSetDevice(prev);
+            return set_error(RICH_EINVAL, "internal check failed: instance %zu's BVH has a leaf of 0 or more than %u triangles",
+                             k, kLeafMaxTris);
+        }
+    }
+    for (size_t k = 0; k < inst.size(); ++k) {
         const uint32_t node_base = (uint32_t)inst_nodes.size(), tri_base = (uint32_t)tris.size();
         for (Node4 nd : knodes[k]) {
             for (int c = 0; c < 4; ++c) {
