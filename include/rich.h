@@ -292,7 +292,9 @@ typedef struct rich_tuning {
  * detector reduced to mirrors, absorbing walls and the photodetector plane,
  * meshed surfaces given as triangles): validates, builds SAH BVH4s (one per
  * mesh instance, in that instance's local frame, with facet normals computed
- * in FP64) and a top-level BVH4, and uploads FP32 copies.  The desc arrays
+ * in FP64) and a top-level BVH4, and uploads FP32 copies.  Every fixed mesh
+ * (segment -1) goes into one instance; each parametrised segment's meshes
+ * into one instance of their own.  The desc arrays
  * are read during the call only; the scene owns its device memory until
  * rich_destroy_scene.  Synchronous.  *out is NULL on failure.
  * Errors: RICH_EINVAL for a NULL pointer, a bad table, an unknown material,
