@@ -22,6 +22,9 @@ constexpr uint32_t kAlwaysLeaf = 1;    // nodes of this many triangles or fewer 
 // of up to kLeafSize triangles becomes a leaf when testing them all costs no
 // more than the node plus the children the split would make.
 constexpr double kNodeCost = 1.0;
+// A group of an instance with several meshes gets its own subtree when its
+// box has at least this fraction of the instance box's surface area.
+constexpr double kLargeGroupArea = 0.1;
 
 struct BNode {
     BuildBox box;
@@ -80,18 +83,37 @@ struct Builder {
     }
 
     // Given groups: an instance that holds several meshes gets one subtree per
-    // group (a plane of a planar mesh, or a whole curved mesh), so that the
-    // SAH never mixes a thin enclosure wall into a mirror's boxes.  Returns the
-    // root, or -1 unless every triangle has a group and there are two or more.
+    // large group (a plane whose box has at least kLargeGroupArea of the
+    // instance box's surface area, such as an enclosure's wall), and one SAH
+    // subtree over all the other triangles, so that the SAH never mixes a thin
+    // enclosure wall into a mirror's boxes.  Nodes whose box holds the ray's
+    // origin cannot be culled; with the walls as the only separate subtrees
+    // the fewest such nodes stand above them.  Returns the root, or -1 unless
+    // every triangle has a group and two or more subtrees result.
     int build_grouped() {
-        std::vector<int> grp(tris.size());
         std::map<int, int> dense;
+        std::vector<int> grp(tris.size());
         for (size_t i = 0; i < tris.size(); ++i) {
             if (tris[i].group < 0) return -1;
             grp[i] = dense.emplace(tris[i].group, (int)dense.size()).first->second;
         }
-        if (dense.size() < 2) return -1;
-        return chain_groups(grp, (int)dense.size());
+        const int ng = (int)dense.size();
+        std::vector<BuildBox> gbox(ng, empty_box());
+        BuildBox all = empty_box();
+        for (size_t i = 0; i < tris.size(); ++i) {
+            grow(gbox[grp[i]], tbox[i]);
+            grow(all, tbox[i]);
+        }
+        std::vector<int> sub(ng, -1);   // subtree of each group; the rest share the last one
+        int n_sub = 0;
+        for (int g = 0; g < ng; ++g)
+            if (area(gbox[g]) >= kLargeGroupArea * area(all)) sub[g] = n_sub++;
+        const bool rest = n_sub < ng;
+        for (int g = 0; g < ng; ++g)
+            if (sub[g] < 0) sub[g] = n_sub;
+        if (n_sub + (rest ? 1 : 0) < 2) return -1;
+        for (auto &v : grp) v = sub[v];
+        return chain_groups(grp, n_sub + (rest ? 1 : 0));
     }
 
     // Planar grouping: a mesh made of a few planes (an enclosure's walls) gets
