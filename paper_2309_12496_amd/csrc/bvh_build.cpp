@@ -408,7 +408,7 @@ uint32_t build_mesh_bvh4(std::vector<BuildTri> &tris, std::vector<Node4> &nodes,
 }
 
 uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &nodes, int *depth) {
-    // binary SAH over instance boxes, treated as degenerate triangles through their corners
+    // binary median splits over instance boxes (largest extent first), one instance per leaf
     std::vector<BuildTri> pseudo(boxes.size());
     for (size_t i = 0; i < boxes.size(); ++i) {
         for (int a = 0; a < 3; ++a) {
@@ -451,9 +451,40 @@ uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &
             return me;
         }
     } tb{pseudo, {}, {}};
-    tb.idx.resize(boxes.size());
-    for (size_t i = 0; i < boxes.size(); ++i) tb.idx[i] = (uint32_t)i;
-    tb.build(0, (uint32_t)boxes.size(), boxes);
+    // An instance whose box has at least kLargeGroupArea of the scene box's
+    // area (the fixed meshes of an enclosure, which hold every ray origin)
+    // hangs from the root itself: a node above it would hold the origin too
+    // and be visited by every query.  Up to three such instances, the rest
+    // in a median-split tree beside them.
+    BuildBox all = empty_box();
+    for (const auto &b : boxes) grow(all, b);
+    std::vector<uint32_t> large, rest;
+    for (size_t i = 0; i < boxes.size(); ++i)
+        (area(boxes[i]) >= kLargeGroupArea * area(all) ? large : rest).push_back((uint32_t)i);
+    int top;
+    if (!large.empty() && large.size() <= 3 && !rest.empty()) {
+        tb.idx = large;
+        tb.idx.insert(tb.idx.end(), rest.begin(), rest.end());
+        const uint32_t nl = (uint32_t)large.size();
+        top = tb.build(nl, (uint32_t)rest.size(), boxes);
+        for (int k = (int)nl - 1; k >= 0; --k) {
+            const int leaf = tb.build((uint32_t)k, 1, boxes);
+            const int me = (int)tb.bn.size();
+            tb.bn.emplace_back();
+            BuildBox box = tb.bn[leaf].box;
+            grow(box, tb.bn[top].box);
+            tb.bn[me].box = box;
+            tb.bn[me].first = (uint32_t)k;
+            tb.bn[me].count = (uint32_t)boxes.size() - (uint32_t)k;
+            tb.bn[me].left = leaf;
+            tb.bn[me].right = top;
+            top = me;
+        }
+    } else {
+        tb.idx.resize(boxes.size());
+        for (size_t i = 0; i < boxes.size(); ++i) tb.idx[i] = (uint32_t)i;
+        top = tb.build(0, (uint32_t)boxes.size(), boxes);
+    }
 
     int maxd = 0;
     std::vector<Node4> &nd = nodes;
@@ -479,7 +510,7 @@ uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &
             return me;
         }
     } te{tb.bn, tb.idx, nd, maxd};
-    uint32_t root = te.emit(0, 1);
+    uint32_t root = te.emit(top, 1);
     if (depth) *depth = maxd;
     return root;
 }
