@@ -37,24 +37,24 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 # Algorithmic VALU work per photon of the headline workload, in 32-bit lane
 # operations: the method's units of work per photon counted on the GPU by the
-# measurement build (26.19 BVH4 nodes, 7.43 triangle tests, 3.72 leaves,
+# measurement build (23.85 BVH4 nodes, 7.43 triangle tests, 3.72 leaves,
 # 2.78 instance entries, 2.78 closest-hit queries, 1.78 reflections, 0.85
 # detector hits, 2 Philox blocks) times the operations each takes
 # (paper_2309_12496_amd/work_counts.py; profiles/work_counts.md).
-ALU_OPS_PER_PHOTON = 3252.1
+ALU_OPS_PER_PHOTON = 3046.2
 # What forward_kernel executes per photon on the same workload (rocprofv3,
 # profiles/forward_kernel_c2_counters.md): SQ_INSTS_VALU x 64 / photons =
 # issued lane slots (inactive lanes of divergent waves included), and
 # SQ_THREAD_CYCLES_VALU / photons = lane operations of active lanes (the
 # counter reads 64 per instruction on a plain copy kernel).
-ISSUED_SLOTS_PER_PHOTON = 6225.6
-ACTIVE_LANE_OPS_PER_PHOTON = 4601.2
+ISSUED_SLOTS_PER_PHOTON = 5916.6
+ACTIVE_LANE_OPS_PER_PHOTON = 4365.7
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch: (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0)
 # KiB per dispatch, scaled by the 256 MiB copy-kernel calibration (262,144 KiB copied: FETCH_SIZE
 # reads 131,086, WRITE_SIZE 262,144), / 1e7 photons (profiles/forward_kernel_c2_counters.md).
-TRAFFIC_BYTES_PER_PHOTON = (1116.7 * 1.9998 + 1134697.0) * 1024 / 1e7
+TRAFFIC_BYTES_PER_PHOTON = (1051.1 * 1.9998 + 1145195.0) * 1024 / 1e7
 
 
 def parse():
