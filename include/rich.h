@@ -29,12 +29,22 @@
  *     tracks' photon total) are read by rich_get_status.
  *   - NULL output pointers mean "do not write".  The histogram, fate counts
  *     and hit-list counter accumulate: the caller zeroes them.
- *   - Launches on one scene share small device counters (the batch work
- *     counter, the fate-count slots, the adjoint partial sums), so work on
- *     one scene must not run concurrently on two streams.  Calls on one
- *     scene from one stream are ordered.  A scene's host state (captured
- *     batch graph, tuning cache) is not locked: one host thread at a time
- *     per scene; different scenes are independent.
+ *   - Each stream that launches on a scene has its own device workspace
+ *     on it (batch work counters, fate-count slots, adjoint partial sums,
+ *     batch processing order, captured batch graph), so launches on one
+ *     scene from different streams may run at the same time.  A stream
+ *     takes one of the scene's 64 workspace slots at its first launch and
+ *     keeps it for the scene's life (a launch from a 65th stream fails with
+ *     RICH_ESTATE); the counters and fate-count slots of every slot are made
+ *     with the scene, so rich_propagate allocates nothing, while the batch
+ *     and adjoint calls grow their stream's buffers with hipMalloc (run them
+ *     once on a stream before capturing that stream into a graph).  A launch
+ *     captured into a graph uses the slot of the stream it was captured on.
+ *     Calls on one scene from one stream are ordered.  The scene's host
+ *     state is locked: host threads may call on one scene at once (the
+ *     calls take turns).  Parameter changes (rich_set_mirror_params,
+ *     rich_fit_step) are ordered on their stream only: launches on other
+ *     streams see them once the caller orders the streams.
  */
 #ifndef RICH_H
 #define RICH_H

@@ -57,6 +57,16 @@ PARAM_SCALE = (1e-3, 1e-3, 10.0, 1.0, 1.0, 1.0)
 FIT_TILTS_RADII = (True, True, True, False, False, False)
 
 
+_CAPTURE_STREAMS = {}
+
+
+def _capture_stream(device):
+    key = torch.device(device)
+    if key not in _CAPTURE_STREAMS:
+        _CAPTURE_STREAMS[key] = torch.cuda.Stream(key)
+    return _CAPTURE_STREAMS[key]
+
+
 def fit_alignment(scene, src, seed, targets, target_mask, params0=None, n=None, steps=600, lr=0.3, lr_final=1e-4,
                   free=FIT_TILTS_RADII, outlier_cut=5.0, cut_floor=1e-3, graph=True, betas=(0.9, 0.999), eps=1e-12):
     """Fit the segment parameters so that the photons' detector hits match `targets`.
@@ -112,10 +122,16 @@ def fit_alignment(scene, src, seed, targets, target_mask, params0=None, n=None, 
         for _ in range(steps):
             step()
     else:
-        step()
+        # the first step runs on the stream the graph is captured on, so that
+        # the library's per-stream work buffer is grown before the capture;
+        # one such stream per device keeps one workspace slot per scene
+        cs = _capture_stream(device)
+        cs.wait_stream(torch.cuda.current_stream(device))
+        with torch.cuda.stream(cs):
+            step()
         torch.cuda.synchronize(device)
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
+        with torch.cuda.graph(g, stream=cs):
             step()
         for _ in range(steps - 1):
             g.replay()

@@ -286,6 +286,26 @@ rich_status valid_tuning(const rich_tuning *t) {
 
 int grid_of(const rich_scene *s, const rich_tuning &t) { return std::max(1, s->n_cu * t.blocks_per_cu); }
 
+// The workspace of the launches on `stream`: the slot the stream took at its
+// first launch on this scene, or a free one (no allocation: the counters
+// and fate-count slots of every slot are made with the scene).  The caller
+// holds the scene's lock.
+rich_status stream_slot(rich_scene *s, hipStream_t stream, StreamWork **out) {
+    for (StreamWork &w : s->slots)
+        if (w.used && w.stream == stream) {
+            *out = &w;
+            return RICH_OK;
+        }
+    for (StreamWork &w : s->slots)
+        if (!w.used) {
+            w.used = true;
+            w.stream = stream;
+            *out = &w;
+            return RICH_OK;
+        }
+    return set_error(RICH_ESTATE, "more than %d streams launch on this scene", kStreamSlots);
+}
+
 rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64_t seed, rich_tuning *best_out) {
     uint64_t n_t = std::min<uint64_t>(n, 4000000ull);
     if (n_t == 0) {
@@ -297,7 +317,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     int32_t *pixel = nullptr;
     float *xyz = nullptr, *uv = nullptr, *time = nullptr;
     uint32_t *hist = nullptr;
-    unsigned long long *counts = nullptr, *counter = nullptr;
+    unsigned long long *counts = nullptr, *counter = nullptr, *tally = nullptr;
     size_t nh = (size_t)s->nx * s->ny;
     hipError_t e = hipSuccess;
     e = e == hipSuccess ? hipMalloc(&fate, n_t) : e;
@@ -308,6 +328,8 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     e = e == hipSuccess ? hipMalloc(&hist, 4 * nh) : e;
     e = e == hipSuccess ? hipMalloc(&counts, 8 * RICH_N_FATES) : e;
     e = e == hipSuccess ? hipMalloc(&counter, 8 * kBatchCounters) : e;
+    e = e == hipSuccess ? hipMalloc(&tally, 8 * kTallyWords) : e;
+    e = e == hipSuccess ? hipMemset(tally, 0, 8 * kTallyWords) : e;
     hipEvent_t a = nullptr, b = nullptr;
     e = e == hipSuccess ? hipEventCreate(&a) : e;
     e = e == hipSuccess ? hipEventCreate(&b) : e;
@@ -324,6 +346,8 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
         out.hit_time = time;
         out.histogram = hist;
         out.fate_counts = counts;
+        DevScene dv = s->dev;   // fate-count slots of its own
+        dv.tally = tally;
         float best = INFINITY;
         rich_tuning bt{256, 256, 4, 0};
         const int blocks[] = {64, 128, 256, 512};
@@ -337,7 +361,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
                     for (int rep = 0; rep < 3 && st == RICH_OK; ++rep) {
                         hipError_t r1 = launch_fill_u64(counter, kBatchCounters, nullptr);
                         (void)hipEventRecord(a, nullptr);
-                        hipError_t r2 = launch_batch(s->dev, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), false, nullptr);
+                        hipError_t r2 = launch_batch(dv, src, out, n_t, seed, counter, blk, ch, grid_of(s, t), false, nullptr);
                         (void)hipEventRecord(b, nullptr);
                         if (r1 != hipSuccess || r2 != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
                             st = set_error(RICH_EDEVICE, "autotune launch failed");
@@ -359,7 +383,7 @@ rich_status run_autotune(rich_scene *s, const DevSource &src, uint64_t n, uint64
     }
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
-    void *ptrs[] = {fate, pixel, xyz, uv, time, hist, counts, counter};
+    void *ptrs[] = {fate, pixel, xyz, uv, time, hist, counts, counter, tally};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     return st;
@@ -469,8 +493,13 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
     if ((st = make_track_source(src, ds))) return st;
     if ((st = set_prefilter(s, src->prefilter, ds))) return st;
     if (n_photons == 0) return RICH_OK;
+    std::lock_guard<std::mutex> lock(s->mu);
+    StreamWork *w = nullptr;
+    if ((st = stream_slot(s, stream, &w))) return st;
     DeviceGuard g(s->device);
-    RICH_HIP(launch_forward(s->dev, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
+    DevScene dv = s->dev;
+    dv.tally = w->tally;
+    RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
     return RICH_OK;
 }
 
@@ -481,6 +510,7 @@ rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_pho
     rich_status st = make_batch_source(batch, ds);
     if (st) return st;
     if ((st = set_prefilter(s, batch->prefilter, ds))) return st;
+    std::lock_guard<std::mutex> lock(s->mu);
     DeviceGuard g(s->device);
     try {
         return run_autotune(s, ds, n_photons, seed, out);
@@ -499,8 +529,13 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
     if ((st = make_batch_source(batch, ds))) return st;
     if ((st = set_prefilter(s, batch->prefilter, ds))) return st;
     if (n_photons == 0) return RICH_OK;
+    std::lock_guard<std::mutex> lock(s->mu);
+    StreamWork *w = nullptr;
+    if ((st = stream_slot(s, stream, &w))) return st;
     DeviceGuard g(s->device);
     try {
+        DevScene dv = s->dev;
+        dv.tally = w->tally;
         rich_tuning t;
         if (tune) {
             if ((st = valid_tuning(tune))) return st;
@@ -527,15 +562,15 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
         const bool ordered = s->dev.has_mesh && n_photons >= (1ull << 21) && batch->n_tracks >= 64;
         if (ordered) {
             const size_t need = order_buffer_bytes(batch->n_tracks);
-            if (need > s->order_bytes) {
-                if (s->d_order) (void)hipFree(s->d_order);
-                s->d_order = nullptr;
-                s->order_bytes = 0;
-                if (hipMalloc(&s->d_order, need) != hipSuccess)
+            if (need > w->order_bytes) {
+                if (w->order) (void)hipFree(w->order);
+                w->order = nullptr;
+                w->order_bytes = 0;
+                if (hipMalloc(&w->order, need) != hipSuccess)
                     return set_error(RICH_ENOMEM, "batch order buffer allocation failed");
-                s->order_bytes = need;
+                w->order_bytes = need;
             }
-            set_order(ds, s->d_order);
+            set_order(ds, w->order);
         }
         // the graph is reused while every launch argument is the same: compare
         // their bytes (both structs are zero-filled before they are set)
@@ -546,33 +581,33 @@ rich_status rich_propagate_batch(rich_scene *s, const rich_batch *batch, uint64_
         put(&n_photons, sizeof n_photons);
         put(&seed, sizeof seed);
         put(&t, sizeof t);
-        if (!s->graph_exec || s->graph_key != k2) {
-            if (s->graph_exec) {
-                (void)hipGraphExecDestroy(s->graph_exec);
-                s->graph_exec = nullptr;
+        if (!w->graph_exec || w->graph_key != k2) {
+            if (w->graph_exec) {
+                (void)hipGraphExecDestroy(w->graph_exec);
+                w->graph_exec = nullptr;
             }
-            if (s->graph) {
-                (void)hipGraphDestroy(s->graph);
-                s->graph = nullptr;
+            if (w->graph) {
+                (void)hipGraphDestroy(w->graph);
+                w->graph = nullptr;
             }
-            if (!s->capture_stream) RICH_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
-            RICH_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e0 = ordered ? launch_order(ds, batch_parts(grid_of(s, t)), s->d_order, s->capture_stream)
+            if (!w->capture_stream) RICH_HIP(hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking));
+            RICH_HIP(hipStreamBeginCapture(w->capture_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e0 = ordered ? launch_order(ds, batch_parts(grid_of(s, t)), w->order, w->capture_stream)
                                     : hipSuccess;
-            hipError_t e1 = launch_fill_u64(s->d_counter, kBatchCounters, s->capture_stream);
-            hipError_t e2 = launch_batch(s->dev, ds, dout, n_photons, seed, s->d_counter, t.block, t.chunk,
-                                         grid_of(s, t), true, s->capture_stream);
+            hipError_t e1 = launch_fill_u64(w->counter, kBatchCounters, w->capture_stream);
+            hipError_t e2 = launch_batch(dv, ds, dout, n_photons, seed, w->counter, t.block, t.chunk,
+                                         grid_of(s, t), true, w->capture_stream);
             hipGraph_t gr = nullptr;
-            hipError_t e3 = hipStreamEndCapture(s->capture_stream, &gr);
+            hipError_t e3 = hipStreamEndCapture(w->capture_stream, &gr);
             if (e0 != hipSuccess || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (gr) (void)hipGraphDestroy(gr);
                 return set_error(RICH_EDEVICE, "graph capture failed");
             }
-            s->graph = gr;
-            RICH_HIP(hipGraphInstantiate(&s->graph_exec, s->graph, nullptr, nullptr, 0));
-            s->graph_key = k2;
+            w->graph = gr;
+            RICH_HIP(hipGraphInstantiate(&w->graph_exec, w->graph, nullptr, nullptr, 0));
+            w->graph_key = k2;
         }
-        RICH_HIP(hipGraphLaunch(s->graph_exec, stream));
+        RICH_HIP(hipGraphLaunch(w->graph_exec, stream));
         return RICH_OK;
     } catch (...) {
         return set_error(RICH_ENOMEM, "batch launch failed");
@@ -600,6 +635,7 @@ static rich_status adjoint_call(rich_scene *s, const rich_source *src, const ric
     if (st) return st;
     if ((st = set_prefilter(s, src ? src->prefilter : batch->prefilter, ds))) return st;
     if (batch && first_photon_id != 0) return set_error(RICH_EINVAL, "batch photons start at id 0");
+    std::lock_guard<std::mutex> lock(s->mu);
     DeviceGuard g(s->device);
     int n_par = 6 * s->n_segments;
     const AdjointPlan plan = adjoint_plan(n_photons, n_par, s->n_cu, dev_mask != nullptr);
@@ -614,17 +650,20 @@ static rich_status adjoint_call(rich_scene *s, const rich_source *src, const ric
         if (e != hipSuccess)
             return set_error(RICH_EDEVICE, "adjoint scratch address: %s", hipGetErrorString(e));
     } else {
-        // grown to the largest call so far: partial sums, mask counts and offsets
+        // the stream's buffer, grown to its largest call so far: partial
+        // sums, mask counts and offsets
+        StreamWork *w = nullptr;
+        if ((st = stream_slot(s, stream, &w))) return st;
         const size_t need = (plan.bytes + sizeof(float) - 1) / sizeof(float);
-        if (need > s->partials_floats) {
-            if (s->d_partials) (void)hipFree(s->d_partials);
-            s->d_partials = nullptr;
-            s->partials_floats = 0;
-            if (hipMalloc(&s->d_partials, need * sizeof(float)) != hipSuccess)
+        if (need > w->partials_floats) {
+            if (w->partials) (void)hipFree(w->partials);
+            w->partials = nullptr;
+            w->partials_floats = 0;
+            if (hipMalloc(&w->partials, need * sizeof(float)) != hipSuccess)
                 return set_error(RICH_ENOMEM, "adjoint work buffer allocation failed");
-            s->partials_floats = need;
+            w->partials_floats = need;
         }
-        work = s->d_partials;
+        work = w->partials;
     }
     AdjointArgs a{dev_grad_uv, dev_targets, dev_mask, dev_residual_cut, nullptr, dev_grad_params, dev_loss, n_par,
                   nullptr, nullptr};

@@ -153,12 +153,15 @@ void free_scene(rich_scene *s) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
-    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
+    for (StreamWork &w : s->slots) {
+        if (w.graph_exec) (void)hipGraphExecDestroy(w.graph_exec);
+        if (w.graph) (void)hipGraphDestroy(w.graph);
+        if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
+        if (w.partials) (void)hipFree(w.partials);
+        if (w.order) (void)hipFree(w.order);
+    }
     void *ptrs[] = {s->d_nodes, s->d_tris, s->d_inst, s->d_caps, s->d_caps_static, s->d_segs, s->d_rects,
-                    s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counter, s->d_partials,
-                    s->d_tally, s->d_order};
+                    s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counters, s->d_tallies};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(prev);
@@ -445,15 +448,19 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     }
     std::vector<CapDev> zero_caps(d->n_caps);
     unsigned int zero_status = 0;
-    std::vector<unsigned long long> zero_counter(kBatchCounters, 0ull);
-    std::vector<unsigned long long> zero_tally(kTallyWords, 0ull);
+    std::vector<unsigned long long> zero_counter((size_t)kStreamSlots * kBatchCounters, 0ull);
+    std::vector<unsigned long long> zero_tally((size_t)kStreamSlots * kTallyWords, 0ull);
     if ((st = upload(&s->d_caps, zero_caps.data(), zero_caps.size(), &bytes)) ||
         (st = upload(&s->d_status, &zero_status, 1, &bytes)) ||
-        (st = upload(&s->d_counter, zero_counter.data(), zero_counter.size(), &bytes)) ||
-        (st = upload(&s->d_tally, zero_tally.data(), zero_tally.size(), &bytes))) {
+        (st = upload(&s->d_counters, zero_counter.data(), zero_counter.size(), &bytes)) ||
+        (st = upload(&s->d_tallies, zero_tally.data(), zero_tally.size(), &bytes))) {
         free_scene(s);
         (void)hipSetDevice(prev);
         return st;
+    }
+    for (int k = 0; k < kStreamSlots; ++k) {
+        s->slots[k].counter = s->d_counters + (size_t)k * kBatchCounters;
+        s->slots[k].tally = s->d_tallies + (size_t)k * kTallyWords;
     }
     PrepareArgs pa{s->d_segs, s->d_caps_static, s->d_params, s->d_caps, d->n_caps, s->d_inst,
                    (int32_t)inst.size(), s->d_nodes, (int32_t)n_top};
@@ -472,7 +479,7 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     S.inst = s->d_inst;
     S.det = s->d_det;
     S.status = s->d_status;
-    S.tally = s->d_tally;
+    S.tally = nullptr;   // the launching stream's fate-count slots, set per call
     S.n_caps = d->n_caps;
     S.n_rects = d->n_rects;
     S.n_mats = d->n_materials;

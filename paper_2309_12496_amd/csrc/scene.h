@@ -4,11 +4,34 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/rich.h"
 #include "rich_dev.h"
+
+namespace rich {
+constexpr int kStreamSlots = 64;   // streams that may launch on one scene
+}  // namespace rich
+
+// Device workspace of the launches made on one stream.  Launches on one
+// scene from different streams may overlap: each stream has its own.
+struct StreamWork {
+    bool used = false;
+    hipStream_t stream = nullptr;               // the launch stream that took this slot
+    unsigned long long *counter = nullptr;      // batch work counters (in the scene's d_counters)
+    unsigned long long *tally = nullptr;        // fate-count slots (in the scene's d_tallies), zero between launches
+    float *partials = nullptr;                  // adjoint partial sums and mask counts, grown
+    size_t partials_floats = 0;
+    void *order = nullptr;                      // batch processing order (cells, tracks, offsets), grown
+    size_t order_bytes = 0;
+    // captured batch graph and the arguments it was captured with
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::string graph_key;
+};
 
 struct rich_scene {
     int device = 0;
@@ -26,12 +49,8 @@ struct rich_scene {
     rich::DetDev *d_det = nullptr;
     float *d_params = nullptr;
     unsigned int *d_status = nullptr;
-    unsigned long long *d_counter = nullptr;   // batch work counter
-    unsigned long long *d_tally = nullptr;     // fate-count slots shared by launches on this scene
-    float *d_partials = nullptr;               // adjoint per-block partial sums
-    size_t partials_floats = 0;
-    void *d_order = nullptr;                   // batch processing order (cells, tracks, offsets)
-    size_t order_bytes = 0;
+    unsigned long long *d_counters = nullptr;  // batch work counters, kBatchCounters per stream slot
+    unsigned long long *d_tallies = nullptr;   // fate-count slots, kTallyWords per stream slot
 
     rich::DevScene dev{};
     std::vector<int32_t> mat_kind;             // host copy of the material kinds
@@ -40,11 +59,8 @@ struct rich_scene {
     int32_t nx = 0, ny = 0;
     rich_scene_stats stats{};
 
-    // captured batch graph and the arguments it was captured with
-    hipStream_t capture_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    std::string graph_key;
+    StreamWork slots[rich::kStreamSlots];
+    std::mutex mu;                             // host calls on the scene, one at a time
 
     // launch shapes chosen by the autotuner, keyed by workload class
     std::map<std::string, rich_tuning> tuned;
