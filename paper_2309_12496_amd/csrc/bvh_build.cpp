@@ -25,6 +25,10 @@ constexpr double kNodeCost = 1.0;
 // A group of an instance with several meshes gets its own subtree when its
 // box has at least this fraction of the instance box's surface area.
 constexpr double kLargeGroupArea = 0.1;
+// Ranges of at least kParallelMin triangles in the top kParallelDepth levels
+// of a subtree build their right half on a thread of its own.
+constexpr int kParallelDepth = 3;
+constexpr uint32_t kParallelMin = 16384;
 
 struct BNode {
     BuildBox box;
@@ -187,8 +191,11 @@ struct Builder {
     int build(uint32_t first, uint32_t count) { return build_into(bn, first, count); }
 
     // Binary SAH subtree over idx[first, first + count), appended to `out`
-    // (child indices are positions in `out`).
-    int build_into(std::vector<BNode> &out, uint32_t first, uint32_t count) {
+    // (child indices are positions in `out`).  The right halves of the top
+    // kParallelDepth splits of large ranges are built on host threads of
+    // their own and appended after the left ones: the same tree, so the same
+    // emitted arrays, as building them in turn.
+    int build_into(std::vector<BNode> &out, uint32_t first, uint32_t count, int depth = 0) {
         int me = (int)out.size();
         out.emplace_back();
         BuildBox box = empty_box(), cb = empty_box();
@@ -254,8 +261,26 @@ struct Builder {
             mid = first + count / 2;  // all centroids coincide: split the index range
         }
         if (mid == first || mid == first + count) mid = first + count / 2;
-        int l = build_into(out, first, mid - first);
-        int r = build_into(out, mid, first + count - mid);
+        int l, r;
+        if (depth < kParallelDepth && count >= kParallelMin) {
+            std::vector<BNode> right;
+            int r_local = -1;
+            std::thread th([&] { r_local = build_into(right, mid, first + count - mid, depth + 1); });
+            l = build_into(out, first, mid - first, depth + 1);
+            th.join();
+            const int base = (int)out.size();
+            for (BNode b : right) {
+                if (b.left >= 0) {
+                    b.left += base;
+                    b.right += base;
+                }
+                out.push_back(b);
+            }
+            r = r_local + base;
+        } else {
+            l = build_into(out, first, mid - first, depth + 1);
+            r = build_into(out, mid, first + count - mid, depth + 1);
+        }
         out[me].left = l;
         out[me].right = r;
         return me;
