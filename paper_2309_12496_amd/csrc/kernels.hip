@@ -314,7 +314,6 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
 // ---------------------------------------------------------------- forward: regrouped groups or grid-stride
 
 constexpr int kForwardBlock = 256;
-constexpr int kForwardBlocksPerCu = 8;
 
 // Regrouping bin of photon g among `bins` bins: its cone azimuth's uniform
 // (word 0 of its first Philox block) in bins 0..bins-2, and the last bin
@@ -415,11 +414,23 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
     if (n == 0) return hipSuccess;
     const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
     const uint64_t per_block = regroup ? kSortGroup : kForwardBlock;
+    const size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) +
+                       kFates * (kForwardBlock / 64) * sizeof(uint32_t) + kSortGroup * sizeof(uint16_t) +
+                       kSortBins * sizeof(uint32_t);
+    // Regrouped photons: one block per resident slot (registers and LDS
+    // decide how many fit on a CU), each looping over its groups; a grid of
+    // more blocks runs in waves of blocks, and a partial last wave leaves
+    // most CUs idle.  Grid-stride photons: two blocks per slot, which
+    // measured faster there.
+    static const int per_cu = [lds] {
+        int b = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, forward_kernel, kForwardBlock, lds) == hipSuccess && b > 0
+                   ? b
+                   : 4;
+    }();
     uint64_t blocks = (n + per_block - 1) / per_block;
-    uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * kForwardBlocksPerCu;
+    const uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * (uint64_t)per_cu * (regroup ? 1u : 2u);
     if (blocks > cap) blocks = cap;
-    size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) + kFates * (kForwardBlock / 64) * sizeof(uint32_t) +
-                 kSortGroup * sizeof(uint16_t) + kSortBins * sizeof(uint32_t);
     hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
                        seed);
     return hipGetLastError();
