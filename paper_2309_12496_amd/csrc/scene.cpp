@@ -196,10 +196,11 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     std::vector<InstanceBuild> inst;
     std::vector<int> seg_inst(d->n_segments, -1);
     int static_inst = -1;
-    // Every fixed mesh goes into one instance.  Its BVH gets a subtree per
-    // group: per plane for a mesh made of a few planes (planes shared by
-    // several meshes, like tiles of one flat mirror, form one group), and per
-    // mesh for the others.
+    // Every fixed mesh goes into one instance.  Its triangles are grouped:
+    // per plane for a mesh made of a few planes (planes shared by several
+    // meshes, like tiles of one flat mirror, form one group), and per mesh
+    // for the others.  The BVH builder gives the large groups (an
+    // enclosure's walls) subtrees of their own and the rest one subtree.
     std::map<PlaneKey, int> plane_group;
     int n_groups = 0;
     uint32_t tri_index = 0;
