@@ -592,3 +592,34 @@ def test_side_stream_launches(R, c2):
         g_s, l_s = R.adjoint(g4, c4["source"], c4["seed"], targets=tgt, stream=side)
     side.synchronize()
     assert np.array_equal(to_np(g_s), to_np(g_ref)) and float(l_s) == float(l_ref)
+
+
+def test_stack_overflow_is_flagged_not_faulted(R, orc):
+    """64 parallel 20 mm squares stacked along z make a planar mesh whose BVH chains one square per
+    group, about 21 BVH4 levels deep.  Listed far to near, every level puts three farther squares on
+    the stack before descending towards the nearest: rays along the stack overflow the 32 entries.
+    The overflow raises RICH_FLAG_STACK_OVERFLOW, the farthest entries are the ones dropped, and
+    every photon still ends on the nearest square as in the oracle.  Listed near to far, the same
+    squares leave the flag clear."""
+    import copy
+    z = 100.0 + 10.0 * np.arange(64)
+    c, n = np.zeros(3), np.array([0.0, 0.0, -1.0])
+    u, v = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    squares = [I.rect_mesh(c + np.array([0.0, 0.0, zk]), n, u, v, 10.0, 10.0, 1, 1) for zk in z]
+    rng = np.random.default_rng(17)
+    m = 256
+    o = np.column_stack([rng.uniform(-5, 5, m), rng.uniform(-5, 5, m), np.zeros(m)])
+    d = np.tile([0.0, 0.0, 1.0], (m, 1))
+    src = I.explicit_source(o, d, np.full(m, 400.0))
+    for far_first, flagged in ((True, True), (False, False)):
+        sc = copy.deepcopy(I.scene_g2())
+        sc["box"] = None
+        tris = np.concatenate(squares[::-1] if far_first else squares)
+        sc["meshes"] = [{"vertices": tris, "material": I.ABSORBER, "segment": -1}]
+        gs = R.Scene(sc)
+        assert gs.info()["max_depth"] >= 16
+        out = R.propagate(gs, src, m, 5)
+        flags = gs.status()
+        assert bool(flags & R.FLAG_STACK_OVERFLOW) == flagged, (far_first, flags)
+        assert (to_np(out["fate"]) == R.ABSORBED).all()
+        compare(out, orc.propagate(sc, src, m, 5), label=f"stacked squares, far first {far_first}")
