@@ -149,15 +149,9 @@ struct Builder {
         // indices rebased (the same tree as building them in turn)
         std::vector<std::vector<BNode>> local(ng);
         std::vector<int> root(ng);
-        std::atomic<int> next{0};
-        auto work = [&]() {
-            for (int r; (r = next.fetch_add(1)) < ng;) root[r] = build_into(local[r], start[r], start[r + 1] - start[r]);
-        };
-        const int n_threads = (int)std::min<unsigned>({(unsigned)ng, std::max(1u, std::thread::hardware_concurrency()), 16u});
-        std::vector<std::thread> pool;
-        for (int i = 1; i < n_threads; ++i) pool.emplace_back(work);
-        work();
-        for (auto &th : pool) th.join();
+        parallel_for((size_t)ng, std::min(16u, std::max(1u, std::thread::hardware_concurrency())), [&](size_t r) {
+            root[r] = build_into(local[r], start[r], start[r + 1] - start[r]);
+        });
         for (int r = 0; r < ng; ++r) {
             const int base = (int)bn.size();
             for (BNode b : local[r]) {
@@ -265,9 +259,10 @@ struct Builder {
         if (depth < kParallelDepth && count >= kParallelMin) {
             std::vector<BNode> right;
             int r_local = -1;
-            std::thread th([&] { r_local = build_into(right, mid, first + count - mid, depth + 1); });
-            l = build_into(out, first, mid - first, depth + 1);
-            th.join();
+            parallel_for(2, 2, [&](size_t half) {
+                if (half == 0) l = build_into(out, first, mid - first, depth + 1);
+                else r_local = build_into(right, mid, first + count - mid, depth + 1);
+            });
             const int base = (int)out.size();
             for (BNode b : right) {
                 if (b.left >= 0) {

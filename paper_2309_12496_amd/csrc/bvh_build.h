@@ -1,7 +1,12 @@
 // Host-side BVH4 construction (binned SAH, FP64) for librich.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "rich_dev.h"
@@ -44,6 +49,36 @@ int plane_groups(const std::vector<BuildTri> &tris, int max_groups, std::vector<
 // Build the top-level BVH4 over instance boxes; leaves reference instances.
 // The nodes are appended to `nodes` starting at the current size.
 uint32_t build_top_bvh4(const std::vector<BuildBox> &boxes, std::vector<Node4> &nodes, int *depth);
+
+// Runs fn(k) for k in [0, n) on up to max_threads host threads, the calling
+// one included.  The first exception a call throws is rethrown here once
+// every thread has been joined (the remaining calls are skipped); if no
+// thread can be started, the calling thread runs them all.
+template <class F>
+void parallel_for(size_t n, size_t max_threads, F &&fn) {
+    std::atomic<size_t> next{0};
+    std::exception_ptr err;
+    std::mutex mu;
+    auto work = [&]() {
+        for (size_t k; (k = next.fetch_add(1)) < n;) {
+            try {
+                fn(k);
+            } catch (...) {
+                std::lock_guard<std::mutex> lock(mu);
+                if (!err) err = std::current_exception();
+                next.store(n);
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    try {
+        for (size_t i = 1; i < std::min(n, max_threads); ++i) pool.emplace_back(work);
+    } catch (...) {
+    }
+    work();
+    for (auto &th : pool) th.join();
+    if (err) std::rethrow_exception(err);
+}
 
 // Outward-rounded FP32 bounds with a small pad against FP32 slab-test rounding.
 float lower_f32(double x);

@@ -168,7 +168,11 @@ void free_scene(rich_scene *s) {
     delete s;
 }
 
-rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) {
+namespace {
+
+// The body of build_scene; *made is the scene once allocated, so that a
+// throw past this point can free it.
+rich_status build_scene_impl(const rich_scene_desc *d, int device, rich_scene **out, rich_scene **made) {
     auto t0 = std::chrono::steady_clock::now();
     rich_status st = validate(d);
     if (st) return st;
@@ -188,6 +192,7 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     }
 
     rich_scene *s = new rich_scene();
+    *made = s;
     s->device = device;
     (void)hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, device);
     int64_t bytes = 0;
@@ -286,17 +291,10 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     std::vector<int> kdepth(inst.size(), 0);
     std::vector<BuildBox> kbox(inst.size());
     {
-        std::atomic<size_t> next{0};
-        auto work = [&]() {
-            for (size_t k; (k = next.fetch_add(1)) < inst.size();)
-                roots[k] = build_mesh_bvh4(inst[k].tris, knodes[k], ktris[k], &kdepth[k], &kbox[k]);
-        };
         const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-        const size_t n_threads = std::min<size_t>({inst.size(), hw, 16});
-        std::vector<std::thread> pool;
-        for (size_t i = 1; i < n_threads; ++i) pool.emplace_back(work);
-        work();
-        for (auto &th : pool) th.join();
+        parallel_for(inst.size(), std::min<size_t>(hw, 16), [&](size_t k) {
+            roots[k] = build_mesh_bvh4(inst[k].tris, knodes[k], ktris[k], &kdepth[k], &kbox[k]);
+        });
     }
     for (size_t k = 0; k < inst.size(); ++k) {
         if (roots[k] == kEmpty) {
@@ -513,6 +511,22 @@ rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) 
     (void)hipSetDevice(prev);
     *out = s;
     return RICH_OK;
+}
+
+}  // namespace
+
+rich_status build_scene(const rich_scene_desc *d, int device, rich_scene **out) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    rich_scene *made = nullptr;
+    try {
+        return build_scene_impl(d, device, out, &made);
+    } catch (...) {
+        // host allocation or thread failure during the build: free what was made
+        if (made && *out != made) free_scene(made);
+        (void)hipSetDevice(prev);
+        throw;
+    }
 }
 
 }  // namespace rich
