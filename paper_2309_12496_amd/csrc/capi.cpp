@@ -493,14 +493,18 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
     if ((st = make_track_source(src, ds))) return st;
     if ((st = set_prefilter(s, src->prefilter, ds))) return st;
     if (n_photons == 0) return RICH_OK;
-    std::lock_guard<std::mutex> lock(s->mu);
-    StreamWork *w = nullptr;
-    if ((st = stream_slot(s, stream, &w))) return st;
-    DeviceGuard g(s->device);
-    DevScene dv = s->dev;
-    dv.tally = w->tally;
-    RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
-    return RICH_OK;
+    try {
+        std::lock_guard<std::mutex> lock(s->mu);
+        StreamWork *w = nullptr;
+        if ((st = stream_slot(s, stream, &w))) return st;
+        DeviceGuard g(s->device);
+        DevScene dv = s->dev;
+        dv.tally = w->tally;
+        RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
+        return RICH_OK;
+    } catch (...) {
+        return set_error(RICH_EDEVICE, "forward launch failed");
+    }
 }
 
 rich_status rich_autotune(rich_scene *s, const rich_batch *batch, uint64_t n_photons, uint64_t seed,
@@ -676,8 +680,12 @@ rich_status rich_propagate_adjoint(rich_scene *s, const rich_source *src, const 
                                    const float *dev_grad_uv, const float *dev_targets, const uint8_t *dev_mask,
                                    const float *dev_residual_cut, float *dev_grad_params, float *dev_loss,
                                    hipStream_t stream) {
-    return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
-                        dev_residual_cut, dev_grad_params, dev_loss, stream, false);
+    try {
+        return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
+                            dev_residual_cut, dev_grad_params, dev_loss, stream, false);
+    } catch (...) {
+        return set_error(RICH_EDEVICE, "adjoint launch failed");
+    }
 }
 
 rich_status rich_propagate_adjoint_noalloc(rich_scene *s, const rich_source *src, const rich_batch *batch,
@@ -685,8 +693,12 @@ rich_status rich_propagate_adjoint_noalloc(rich_scene *s, const rich_source *src
                                            const float *dev_grad_uv, const float *dev_targets,
                                            const uint8_t *dev_mask, const float *dev_residual_cut,
                                            float *dev_grad_params, float *dev_loss, hipStream_t stream) {
-    return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
-                        dev_residual_cut, dev_grad_params, dev_loss, stream, true);
+    try {
+        return adjoint_call(s, src, batch, n_photons, seed, first_photon_id, dev_grad_uv, dev_targets, dev_mask,
+                            dev_residual_cut, dev_grad_params, dev_loss, stream, true);
+    } catch (...) {
+        return set_error(RICH_EDEVICE, "adjoint launch failed");
+    }
 }
 
 // Gauss-Legendre rule on [-1, 1]: nodes are the roots of P_n, found by Newton
