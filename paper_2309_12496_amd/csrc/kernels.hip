@@ -202,9 +202,20 @@ hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st) {
 // Trace photon g (output slot i), write its results and return its fate (-1
 // for inactive lanes).  Every lane of the wave must call this together: the
 // hit list uses wave-wide ballots.
+// Per-photon output store.  kStream: a non-temporal store, which L2 keeps
+// for a short time only, so that a large batch's gigabytes of outputs do
+// not push the scene out of L2 (the batch kernel; the forward kernel writes
+// each line in several passes and keeps them in L2 to merge).
+template <bool kStream, class T>
+__device__ __forceinline__ void put(T *p, T v) {
+    if constexpr (kStream) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // kConstDet: read the detector through the constant address space (scalar
 // loads).  The forward kernel gains from it; the batch kernel, held to 128
-// VGPRs, spills the extra scalar state and reads the detector per lane.
+// VGPRs, spills the extra scalar state and reads the detector per lane.  The
+// batch kernel (kConstDet false) streams its outputs past L2.
 template <bool kConstDet>
 __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
                                           uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk,
@@ -227,20 +238,22 @@ __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &sr
         if constexpr (kConstDet) run(cref(*S.det));
         else run(*S.det);
         bool on_det = end.fate == kDetected || end.fate == kQeRejected;
-        if (out.fate) out.fate[i] = (uint8_t)end.fate;
-        if (out.pixel) out.pixel[i] = on_det ? end.pixel : -1;
+        constexpr bool kStream = !kConstDet;
+        const float nan = __builtin_nanf("");
+        if (out.fate) put<kStream>(out.fate + i, (uint8_t)end.fate);
+        if (out.pixel) put<kStream>(out.pixel + i, on_det ? end.pixel : -1);
         if (out.hit_xyz) {
             float *p = out.hit_xyz + 3 * i;
-            p[0] = on_det ? end.P.x : __builtin_nanf("");
-            p[1] = on_det ? end.P.y : __builtin_nanf("");
-            p[2] = on_det ? end.P.z : __builtin_nanf("");
+            put<kStream>(p, on_det ? end.P.x : nan);
+            put<kStream>(p + 1, on_det ? end.P.y : nan);
+            put<kStream>(p + 2, on_det ? end.P.z : nan);
         }
         if (out.hit_uv) {
             float *p = out.hit_uv + 2 * i;
-            p[0] = on_det ? end.u : __builtin_nanf("");
-            p[1] = on_det ? end.v : __builtin_nanf("");
+            put<kStream>(p, on_det ? end.u : nan);
+            put<kStream>(p + 1, on_det ? end.v : nan);
         }
-        if (out.hit_time) out.hit_time[i] = on_det ? end.time : __builtin_nanf("");
+        if (out.hit_time) put<kStream>(out.hit_time + i, on_det ? end.time : nan);
         if (out.histogram && end.fate == kDetected) atomicAdd(out.histogram + end.pixel, 1u);
     }
     if (out.hit_list) {
