@@ -693,7 +693,10 @@ extern "C" int rich_work_counters_adjoint(unsigned long long *out, int reset) {
     unsigned long long raw[16 * rich::kWorkUnits];
     if (hipDeviceSynchronize() != hipSuccess) return -3;
     if (hipMemcpyFromSymbol(raw, HIP_SYMBOL(rich::rich_work), sizeof raw) != hipSuccess) return -3;
-    for (int u = 0; u < rich::kWorkUnits; ++u) out[u] = raw[16 * u];
+    for (int u = 0; u < rich::kWorkUnits; ++u) {
+        out[u] = raw[16 * u];
+        out[rich::kWorkUnits + u] = raw[16 * u + 1];
+    }
     if (reset) {
         unsigned long long zero[16 * rich::kWorkUnits] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(rich::rich_work), zero, sizeof zero) != hipSuccess) return -3;

@@ -719,13 +719,16 @@ hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutput
 
 #ifdef RICH_WORK_COUNTERS
 // Measurement build only: copy the forward and batch kernels' work counters
-// (WorkUnit order, kWorkUnits values) to the host, then zero them when reset
-// is set.  Synchronises the current device.
+// to the host (WorkUnit order: kWorkUnits lane counts, then kWorkUnits wave
+// counts), then zero them when reset is set.  Synchronises the current device.
 extern "C" int rich_work_counters(unsigned long long *out, int reset) {
     unsigned long long raw[16 * rich::kWorkUnits];
     if (hipDeviceSynchronize() != hipSuccess) return -3;
     if (hipMemcpyFromSymbol(raw, HIP_SYMBOL(rich::rich_work), sizeof raw) != hipSuccess) return -3;
-    for (int u = 0; u < rich::kWorkUnits; ++u) out[u] = raw[16 * u];
+    for (int u = 0; u < rich::kWorkUnits; ++u) {
+        out[u] = raw[16 * u];
+        out[rich::kWorkUnits + u] = raw[16 * u + 1];
+    }
     if (reset) {
         unsigned long long zero[16 * rich::kWorkUnits] = {};
         if (hipMemcpyToSymbol(HIP_SYMBOL(rich::rich_work), zero, sizeof zero) != hipSuccess) return -3;

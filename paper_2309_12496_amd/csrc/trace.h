@@ -52,7 +52,9 @@ __device__ __forceinline__ float comp(V3 a, int k) { return k == 0 ? a.x : (k ==
 // instance's frame (and apart those that rotate and scale the ray), a
 // reflection, a detector hit; in the adjoint, a counted photon's pass back
 // through the detector plane and each reflection it sweeps back through (cap
-// or facet).  Lanes of a wave are summed with one atomic per counter and wave.
+// or facet).  Lanes of a wave are summed with one atomic per counter and wave;
+// a second word in the counter's line counts the waves that did the unit, so
+// lanes / (64 x waves) is the unit's SIMD efficiency.
 enum WorkUnit {
     kWorkPhotons, kWorkPhilox, kWorkSortKeys, kWorkQueries, kWorkCapBoxes, kWorkCaps, kWorkRects, kWorkBoxes,
     kWorkNodes, kWorkLeaves, kWorkTris, kWorkInstances, kWorkMovingInstances, kWorkReflections, kWorkDetections,
@@ -62,7 +64,10 @@ enum WorkUnit {
 static __device__ unsigned long long rich_work[16 * kWorkUnits];   // one 128-byte line per counter
 __device__ __forceinline__ void work(int unit) {
     const unsigned long long m = __ballot(1);
-    if (__lane_id() == __ffsll((long long)m) - 1) atomicAdd(&rich_work[16 * unit], (unsigned long long)__popcll(m));
+    if (__lane_id() == __ffsll((long long)m) - 1) {
+        atomicAdd(&rich_work[16 * unit], (unsigned long long)__popcll(m));
+        atomicAdd(&rich_work[16 * unit + 1], 1ull);
+    }
 }
 #else
 __device__ __forceinline__ void work(int) {}

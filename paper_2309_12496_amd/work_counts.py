@@ -7,8 +7,10 @@ box tests, BVH4 nodes whose four child boxes it tests, leaves, triangle
 tests, instance entries, reflections, detector hits), summed per wave with
 one atomic per counter.  Photons and outputs are those of the product build;
 only the counters are added.  This script runs each workload once through it
-and prints the counts per traced photon, and the algorithmic VALU work per
-photon formed from them (units x operations per unit, OPS_PER_UNIT).
+and prints the counts per traced photon, the algorithmic VALU work per
+photon formed from them (units x operations per unit, OPS_PER_UNIT), and each
+unit's SIMD efficiency: the share of a wave's 64 lanes that did the unit
+when the wave did it.
 
     python -m paper_2309_12496_amd.build_lib --work-counters   # on the CPU, once
     python -m paper_2309_12496_amd.work_counts [c1 c2 c3 c4 c5] # on the GPU
@@ -126,13 +128,22 @@ def main(which):
     lib = C.CDLL(WORK_LIB)
     lib.rich_work_counters.argtypes = [C.POINTER(C.c_ulonglong), C.c_int]
     lib.rich_work_counters_adjoint.argtypes = [C.POINTER(C.c_ulonglong), C.c_int]
-    raw = (C.c_ulonglong * len(UNITS))()
+    raw = (C.c_ulonglong * (2 * len(UNITS)))()
 
     def read(adjoint=False):
+        """Lane counts per unit; the wave counts that follow them go to waves."""
         fn = lib.rich_work_counters_adjoint if adjoint else lib.rich_work_counters
         if fn(raw, 1) != 0:
             raise RuntimeError("rich_work_counters failed")
-        return list(raw)
+        waves.clear()
+        waves.update(zip(UNITS, raw[len(UNITS):]))
+        return list(raw[:len(UNITS)])
+
+    waves = {}
+
+    def efficiency(counts):
+        """Per unit, the active lanes of the waves that did it: lanes / (64 x waves)."""
+        return {u: round(counts[u] / (64 * waves[u]), 3) for u in UNITS if waves.get(u)}
 
     out = {}
     for name in which:
@@ -150,7 +161,8 @@ def main(which):
         n = counts["photons"]
         per = {u: counts[u] / n for u in UNITS}
         out[cfg["name"]] = {"traced_photons": n, "per_photon": {u: round(v, 4) for u, v in per.items()},
-                            "algorithmic_ops_per_photon": round(algorithmic_ops(per), 1)}
+                            "algorithmic_ops_per_photon": round(algorithmic_ops(per), 1),
+                            "simd_efficiency": efficiency(counts)}
         print(json.dumps({cfg["name"]: out[cfg["name"]]}), flush=True)
         if k in (4, 5):
             # the adjoint of the forward + adjoint form: targets at the seeded
@@ -169,7 +181,8 @@ def main(which):
             per = {u: counts[u] / m for u in UNITS}
             key = cfg["name"] + ", adjoint"
             out[key] = {"masked_photons": m, "per_photon": {u: round(v, 4) for u, v in per.items()},
-                        "algorithmic_ops_per_photon": round(algorithmic_ops(per), 1)}
+                        "algorithmic_ops_per_photon": round(algorithmic_ops(per), 1),
+                        "simd_efficiency": efficiency(counts)}
             print(json.dumps({key: out[key]}), flush=True)
             del mask, targets
         del res, scene
