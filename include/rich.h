@@ -31,14 +31,17 @@
  *     and hit-list counter accumulate: the caller zeroes them.
  *   - Each stream that launches on a scene has its own device workspace
  *     on it (batch work counters, fate-count slots, adjoint partial sums,
- *     batch processing order, captured batch graph), so launches on one
- *     scene from different streams may run at the same time.  A stream
- *     takes one of the scene's 64 workspace slots at its first launch and
- *     keeps it for the scene's life (a launch from a 65th stream fails with
- *     RICH_ESTATE); the counters and fate-count slots of every slot are made
- *     with the scene, so rich_propagate allocates nothing, while the batch
- *     and adjoint calls grow their stream's buffers with hipMalloc (run them
- *     once on a stream before capturing that stream into a graph).  A launch
+ *     forward and batch processing orders, captured batch graph), so
+ *     launches on one scene from different streams may run at the same
+ *     time.  A stream takes one of the scene's 64 workspace slots at its
+ *     first launch and keeps it for the scene's life (a launch from a 65th
+ *     stream fails with RICH_ESTATE); the counters and fate-count slots of
+ *     every slot are made with the scene, while the calls grow their
+ *     stream's buffers with hipMalloc: rich_propagate on a meshed scene (or
+ *     with the pre-filter) its photon order, 4 bytes per photon up to 2^24
+ *     photons, and the batch and adjoint calls theirs (run a call once on a
+ *     stream, at its largest size, before capturing that stream into a
+ *     graph; rich_propagate on an analytic scene allocates nothing).  A launch
  *     captured into a graph uses the slot of the stream it was captured on.
  *     Calls on one scene from one stream are ordered.  The scene's host
  *     state is locked: host threads may call on one scene at once (the
@@ -338,11 +341,16 @@ rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipSt
  * the surface as Section 7 proposes), and the detector hit as global point,
  * (u, v) and pixel (Section 4.4); the compact hit list is Section 7's list of
  * global hits.  Every output array is the caller's device memory, indexed by
- * g - first_photon_id; NULL skips it.  Asynchronous on `stream`.
+ * g - first_photon_id; NULL skips it.  Asynchronous on `stream`.  On meshed
+ * scenes and with the pre-filter the photons are traced in an order sorted
+ * by cone azimuth within windows of 8192 ids (a sort kernel runs first, into
+ * the stream's order buffer), in launches of at most 2^24 photons; results
+ * do not depend on the order.
  * Errors (synchronous, nothing launched): RICH_EINVAL for NULL scene or
  * source, an unknown source kind, n beta <= 1, a bad table or prefilter
  * material, a hit list without its counter; RICH_ERANGE when the id range
- * wraps 2^64 or n_photons > 2^40; RICH_EDEVICE when the launch fails.
+ * wraps 2^64 or n_photons > 2^40; RICH_ENOMEM when the stream's order buffer
+ * cannot grow; RICH_EDEVICE when the launch fails.
  * Traversal-stack and hit-list overflow raise device flags
  * (rich_get_status). */
 rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_photons, uint64_t seed,

@@ -23,7 +23,7 @@
 // dealt round robin, the size that loads the busiest wave least; every pass
 // but the last is full.  A group of 128 or 256 is sorted by cone azimuth (a
 // counting sort in lane order) and traced in passes of 64, so that each pass
-// holds neighbouring rays, as the forward kernel regroups.
+// holds neighbouring rays, as the forward launch sorts its photons.
 //
 // Sums are deterministic: groups map statically to waves and the regrouping
 // order is fixed; per segment the wave reduces with a butterfly and lane 0

@@ -500,7 +500,20 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
         DeviceGuard g(s->device);
         DevScene dv = s->dev;
         dv.tally = w->tally;
-        RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, stream));
+        if (forward_sorted(dv, ds)) {
+            // the stream's order buffer, grown to the largest chunk so far
+            const uint64_t need = n_photons < kSortedChunk ? n_photons : kSortedChunk;
+            if (need > w->sorted_count) {
+                if (w->sorted) (void)hipFree(w->sorted);
+                w->sorted = nullptr;
+                w->sorted_count = 0;
+                if (hipMalloc(&w->sorted, need * sizeof(uint32_t)) != hipSuccess)
+                    return set_error(RICH_ENOMEM, "forward order buffer allocation failed");
+                w->sorted_count = need;
+            }
+        }
+        RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, w->sorted,
+                                stream));
         return RICH_OK;
     } catch (...) {
         return set_error(RICH_EDEVICE, "forward launch failed");

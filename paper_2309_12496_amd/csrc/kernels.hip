@@ -324,7 +324,7 @@ __device__ __forceinline__ void flush_tally(const DevScene &S, const DevOutputs 
     }
 }
 
-// ---------------------------------------------------------------- forward: regrouped groups or grid-stride
+// ---------------------------------------------------------------- forward: sorted order or grid-stride
 
 constexpr int kForwardBlock = 256;
 
@@ -348,20 +348,80 @@ __device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSour
     return b < top ? b : top - 1u;
 }
 
-constexpr int kSortGroup = 1024;   // photons regrouped together by cone azimuth
-constexpr int kSortBins = 128;     // a multiple of 64
-static_assert(kSortBins % 64 == 0 && kSortGroup % kForwardBlock == 0 && kSortGroup % 2 == 0 && kSortGroup <= 65536,
-              "regrouping shape");
+// Photons of a forward launch are traced in an order sorted by cone azimuth
+// within windows of kSortWindow ids: sort_photons_kernel counting-sorts each
+// window by the azimuth's uniform (word 0 of the photon's first Philox block;
+// the photons the pre-filter rejects last) into kSortBins bins, and the trace
+// kernel's waves then take 64 neighbours in that order, whose rays meet the
+// same parts of the scene.  Every photon keeps its id and random numbers and
+// writes its outputs at its id; only the lane that traces it changes.
+constexpr int kSortWindow = 8192;
+constexpr int kSortBins = 1024;
+constexpr int kSortThreads = 1024;
+static_assert(kSortWindow % kSortThreads == 0 && kSortBins % kSortThreads == 0 && kSortWindow <= 65536 &&
+                  kSortedChunk % kSortWindow == 0 && kSortedChunk <= (uint64_t(1) << 32),
+              "sort shape");
+
+__global__ __launch_bounds__(kSortThreads) void sort_photons_kernel(DevScene S, DevSource src, uint64_t n,
+                                                                    uint64_t first, uint64_t seed, uint32_t *sorted) {
+    __shared__ uint32_t bins[kSortBins];
+    __shared__ uint16_t slot[kSortWindow];
+    __shared__ uint32_t wave_sum[kSortThreads / 64];
+    constexpr int per = kSortWindow / kSortThreads;
+    const uint64_t w0 = (uint64_t)blockIdx.x * kSortWindow;
+    const uint32_t m = (uint32_t)(n - w0 < (uint64_t)kSortWindow ? n - w0 : (uint64_t)kSortWindow);
+    for (int q = threadIdx.x; q < kSortBins; q += kSortThreads) bins[q] = 0;
+    __syncthreads();
+    // bin and rank within the bin (16 bits each) of this thread's photons
+    uint32_t key[per];
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        const uint32_t l = (uint32_t)(j * kSortThreads) + threadIdx.x;
+        key[j] = 0;
+        if (l < m) {
+            const uint32_t b = regroup_bin(S, src, seed, first + w0 + l, w0 + l, kSortBins);
+            key[j] = b | (atomicAdd(bins + b, 1u) << 16);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the bin counts: per thread, then per wave, then across waves
+    constexpr int bpt = kSortBins / kSortThreads;
+    uint32_t c[bpt], sum = 0;
+#pragma unroll
+    for (int q = 0; q < bpt; ++q) {
+        c[q] = bins[bpt * threadIdx.x + q];
+        sum += c[q];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = sum;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    if (lane == 63) wave_sum[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += wave_sum[w];
+#pragma unroll
+    for (int q = 0; q < bpt; ++q) {
+        bins[bpt * threadIdx.x + q] = run;
+        run += c[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        const uint32_t l = (uint32_t)(j * kSortThreads) + threadIdx.x;
+        if (l < m) slot[bins[key[j] & 0xFFFFu] + (key[j] >> 16)] = (uint16_t)l;
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < m; q += kSortThreads) sorted[w0 + q] = (uint32_t)(w0 + slot[q]);
+}
 
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
-                                                                uint64_t first, uint64_t seed) {
+                                                                uint64_t first, uint64_t seed, const uint32_t *sorted) {
     extern __shared__ uint32_t lds_stack[];
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
-    // slot indices of the regrouped group (16 bits: kSortGroup <= 65536), then the bins
-    uint16_t *perm = reinterpret_cast<uint16_t *>(lds_stack + (size_t)blockDim.x * kStackDepth + kFates * (blockDim.x / 64));
-    uint32_t *bins = reinterpret_cast<uint32_t *>(perm + kSortGroup);
-    const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
-    if (!regroup) {
+    if (!sorted) {
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
             uint64_t i = base + threadIdx.x;
@@ -369,84 +429,78 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
             if (out.fate_counts) tally_wave(cnt, fate);
         }
     } else {
-        // Photons of one group whose cone azimuths are close meet the same
-        // parts of the scene: counting-sort the group by the azimuth's
-        // uniform (word 0 of the photon's first Philox block), with the
-        // photons the pre-filter rejects in the last bin, so that each wave
-        // traces neighbours and kept photons fill whole waves.  Every photon
-        // keeps its own id and random numbers; only the lane that traces it
-        // changes.
-        constexpr int per = kSortGroup / kForwardBlock;
-        const uint64_t stride = (uint64_t)gridDim.x * kSortGroup;
-        for (uint64_t base = (uint64_t)blockIdx.x * kSortGroup; base < n; base += stride) {
-            for (int q = threadIdx.x; q < kSortBins; q += kForwardBlock) bins[q] = 0;
-            __syncthreads();
-            uint32_t bin[per], rank[per];
-            for (int j = 0; j < per; ++j) {
-                const uint64_t i = base + (uint64_t)(j * kForwardBlock + threadIdx.x);
-                bin[j] = i < n ? regroup_bin(S, src, seed, first + i, i, kSortBins) : kSortBins - 1;
-                rank[j] = atomicAdd(bins + bin[j], 1u);
-            }
-            __syncthreads();
-            if (threadIdx.x < 64) {   // exclusive scan of the bin counts by one wave, kSortBins / 64 per lane
-                constexpr int bpl = kSortBins / 64;
-                uint32_t c[bpl], sum = 0;
-#pragma unroll
-                for (int q = 0; q < bpl; ++q) {
-                    c[q] = bins[bpl * threadIdx.x + q];
-                    sum += c[q];
-                }
-                uint32_t incl = sum;
-                for (int d = 1; d < 64; d <<= 1) {
-                    uint32_t v = __shfl_up(incl, d);
-                    if ((int)threadIdx.x >= d) incl += v;
-                }
-                uint32_t run = incl - sum;
-#pragma unroll
-                for (int q = 0; q < bpl; ++q) {
-                    bins[bpl * threadIdx.x + q] = run;
-                    run += c[q];
-                }
-            }
-            __syncthreads();
-            for (int j = 0; j < per; ++j) perm[bins[bin[j]] + rank[j]] = (uint16_t)(j * kForwardBlock + threadIdx.x);
-            __syncthreads();
-            for (int j = 0; j < per; ++j) {
-                const uint64_t i = base + perm[j * kForwardBlock + threadIdx.x];
-                int fate = photon_job<true>(S, src, out, i < n, i, first + i, seed, lane_stack(lds_stack));
-                if (out.fate_counts) tally_wave(cnt, fate);
-            }
-            __syncthreads();
+        // The sorted positions are split into one contiguous range per XCD
+        // (workgroups are dealt to the eight XCDs round robin), so that an
+        // XCD's photons in flight are neighbours in the sorted order and
+        // their outputs lie in few windows.  Within its XCD a block takes
+        // one 256-position slice of each chunk of the range, a different
+        // slice each time: the slices of a window differ in azimuth and so
+        // in cost, and every block should see all of them.
+        const uint32_t parts = gridDim.x >= 8 ? 8u : 1u;
+        const uint32_t x = blockIdx.x % parts, jb = blockIdx.x / parts, nx = (gridDim.x - x + parts - 1) / parts;
+        const uint64_t span = (n + (uint64_t)parts * kForwardBlock - 1) / ((uint64_t)parts * kForwardBlock) * kForwardBlock;
+        const uint64_t lo = (uint64_t)x * span, hi = lo + span < n ? lo + span : n;
+        const uint64_t chunk = (uint64_t)nx * kForwardBlock;
+        for (uint64_t t = 0; lo + t * chunk < hi; ++t) {
+            const uint64_t k = lo + t * chunk + (uint64_t)((jb + t * 41u) % nx) * kForwardBlock + threadIdx.x;
+            const bool active = k < hi;
+            const uint64_t i = active ? sorted[k] : 0;
+            int fate = photon_job<true>(S, src, out, active, i, first + i, seed, lane_stack(lds_stack));
+            if (out.fate_counts) tally_wave(cnt, fate);
         }
     }
     if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
 
+bool forward_sorted(const DevScene &S, const DevSource &src) {
+    return (S.has_mesh && src.kind != 2) || src.prefilter;
+}
+
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
-                          uint64_t seed, int n_cu, hipStream_t st) {
+                          uint64_t seed, int n_cu, uint32_t *sorted, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const bool regroup = (S.has_mesh && src.kind != 2) || src.prefilter;
-    const uint64_t per_block = regroup ? kSortGroup : kForwardBlock;
+    const bool sort = forward_sorted(S, src);
+    if (sort && !sorted) return hipErrorInvalidValue;
     const size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) +
-                       kFates * (kForwardBlock / 64) * sizeof(uint32_t) + kSortGroup * sizeof(uint16_t) +
-                       kSortBins * sizeof(uint32_t);
-    // Regrouped photons: one block per resident slot (registers and LDS
-    // decide how many fit on a CU), each looping over its groups; a grid of
-    // more blocks runs in waves of blocks, and a partial last wave leaves
-    // most CUs idle.  Grid-stride photons: two blocks per slot, which
-    // measured faster there.
+                       kFates * (kForwardBlock / 64) * sizeof(uint32_t);
+    // One block per resident slot (registers and LDS decide how many fit on
+    // a CU), each looping over its photons; a grid of more blocks runs in
+    // waves of blocks, and a partial last wave leaves most CUs idle.  Unsorted
+    // (analytic) launches take two blocks per slot, which measured faster
+    // there.  A sorted grid is a multiple of the eight XCDs.
     static const int per_cu = [lds] {
         int b = 0;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, forward_kernel, kForwardBlock, lds) == hipSuccess && b > 0
                    ? b
                    : 4;
     }();
-    uint64_t blocks = (n + per_block - 1) / per_block;
-    const uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * (uint64_t)per_cu * (regroup ? 1u : 2u);
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, out, n, first,
-                       seed);
-    return hipGetLastError();
+    const uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * (uint64_t)per_cu * (sort ? 1u : 2u);
+    // sorted launches go in chunks of at most kSortedChunk photons (the order
+    // buffer's size); the outputs of a chunk start at its first photon
+    const uint64_t step = sort ? kSortedChunk : n;
+    for (uint64_t off = 0; off < n; off += step) {
+        const uint64_t m = n - off < step ? n - off : step;
+        DevOutputs o = out;   // every per-photon output is optional
+        if (o.fate) o.fate += off;
+        if (o.pixel) o.pixel += off;
+        if (o.hit_xyz) o.hit_xyz += 3 * off;
+        if (o.hit_uv) o.hit_uv += 2 * off;
+        if (o.hit_time) o.hit_time += off;
+        uint64_t blocks = (m + kForwardBlock - 1) / kForwardBlock;
+        if (blocks > cap) blocks = cap;
+        if (sort) {
+            if (blocks >= 8) blocks -= blocks % 8;
+            hipLaunchKernelGGL(sort_photons_kernel, dim3((unsigned)((m + kSortWindow - 1) / kSortWindow)),
+                               dim3(kSortThreads), 0, st, S, src, m, first + off, seed, sorted);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, o, m,
+                           first + off, seed, (const uint32_t *)(sort ? sorted : nullptr));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------- batch: processing order

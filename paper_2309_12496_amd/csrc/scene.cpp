@@ -159,6 +159,7 @@ void free_scene(rich_scene *s) {
         if (w.capture_stream) (void)hipStreamDestroy(w.capture_stream);
         if (w.partials) (void)hipFree(w.partials);
         if (w.order) (void)hipFree(w.order);
+        if (w.sorted) (void)hipFree(w.sorted);
     }
     void *ptrs[] = {s->d_nodes, s->d_tris, s->d_inst, s->d_caps, s->d_caps_static, s->d_segs, s->d_rects,
                     s->d_mats, s->d_det, s->d_params, s->d_status, s->d_counters, s->d_tallies};

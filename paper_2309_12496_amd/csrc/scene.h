@@ -26,6 +26,8 @@ struct StreamWork {
     size_t partials_floats = 0;
     void *order = nullptr;                      // batch processing order (cells, tracks, offsets), grown
     size_t order_bytes = 0;
+    uint32_t *sorted = nullptr;                 // forward photon order (one chunk's ids), grown
+    uint64_t sorted_count = 0;
     // captured batch graph and the arguments it was captured with
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;

@@ -116,6 +116,50 @@ def test_split_ranges_are_bit_identical(R, c2):
     assert np.array_equal(to_np(full["histogram"]), to_np(a["histogram"]) + to_np(b["histogram"]))
 
 
+def test_sorted_launch_beyond_one_chunk(R, orc, c2):
+    """A forward launch on a meshed scene traces its photons in an order sorted by cone azimuth, in
+    chunks of 2^24 photons (the order buffer's size).  One call of 2^24 + 4321 photons (two chunks,
+    the second a ragged window) equals, bit for bit, the same ids traced by two calls split elsewhere;
+    the photons of the second chunk match the oracle."""
+    import torch
+    cfg, gs, os_ = c2
+    chunk = 1 << 24
+    n, cut = chunk + 4321, 10_000_000
+    full = R.propagate(gs, cfg["source"], n, cfg["seed"])
+    a = R.propagate(gs, cfg["source"], cut, cfg["seed"], first_id=0)
+    b = R.propagate(gs, cfg["source"], n - cut, cfg["seed"], first_id=cut)
+    for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time"):
+        fk = to_np(full[k])
+        assert np.array_equal(fk, np.concatenate([to_np(a[k]), to_np(b[k])]), equal_nan=fk.dtype.kind == "f"), k
+    assert np.array_equal(to_np(full["fate_counts"]), to_np(a["fate_counts"]) + to_np(b["fate_counts"]))
+    assert np.array_equal(to_np(full["histogram"]), to_np(a["histogram"]) + to_np(b["histogram"]))
+    assert int(to_np(full["fate_counts"]).sum()) == n
+    tail = {k: v[chunk:] for k, v in full.items() if k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    ref = orc.propagate(os_, cfg["source"], n - chunk, cfg["seed"], first_id=chunk)
+    compare(tail, ref, min_agree=0.999, label="C2 second chunk")
+    del full, a, b
+    torch.cuda.empty_cache()
+    assert gs.status() == 0
+
+
+def test_sorted_launch_with_outputs_left_out(R, c2):
+    """Every per-photon output is optional: a sorted launch that asks only for the arrival times
+    (and the fate counts) writes the same times as one that asks for everything."""
+    import torch
+    cfg, gs, _ = c2
+    n = 100_000
+    ref = R.propagate(gs, cfg["source"], n, cfg["seed"])
+    s, keep = R.make_source(cfg["source"])
+    t, o = R.alloc_outputs(gs, n)
+    for f in ("fate", "pixel", "hit_xyz", "hit_uv"):
+        setattr(o, f, None)
+    R.rich_propagate(gs.handle, s, n, cfg["seed"], 0, o)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(t["hit_time"]), to_np(ref["hit_time"]), equal_nan=True)
+    assert np.array_equal(to_np(t["fate_counts"]), to_np(ref["fate_counts"]))
+    assert gs.status() == 0
+
+
 def test_c2_meshed_subset_at_full_size(R, orc, c2):
     """The 1e7-photon launch as the benchmark runs it; every 100th photon checked against the oracle."""
     cfg, gs, os_ = c2
