@@ -357,7 +357,7 @@ __device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSour
 // writes its outputs at its id; only the lane that traces it changes.
 constexpr int kSortWindow = 8192;
 constexpr int kSortBins = 1024;
-constexpr int kSortThreads = 1024;
+constexpr int kSortThreads = 256;
 static_assert(kSortWindow % kSortThreads == 0 && kSortBins % kSortThreads == 0 && kSortWindow <= 65536 &&
                   kSortedChunk % kSortWindow == 0 && kSortedChunk <= (uint64_t(1) << 32),
               "sort shape");
