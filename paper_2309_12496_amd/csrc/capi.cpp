@@ -513,7 +513,7 @@ rich_status rich_propagate(rich_scene *s, const rich_source *src, uint64_t n_pho
             }
         }
         RICH_HIP(launch_forward(dv, ds, make_outputs(out), n_photons, first_photon_id, seed, s->n_cu, w->sorted,
-                                stream));
+                                w->counter, stream));
         return RICH_OK;
     } catch (...) {
         return set_error(RICH_EDEVICE, "forward launch failed");

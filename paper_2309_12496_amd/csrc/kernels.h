@@ -21,19 +21,22 @@ struct PrepareArgs {
 
 hipError_t launch_prepare(const PrepareArgs &a, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, int n, hipStream_t st);
+// Work counters of the batch and sorted forward kernels: one per id
+// partition, a 128-byte line apart.
+constexpr int kBatchParts = 8;
+constexpr int kCounterStride = 16;
+constexpr int kBatchCounters = kBatchParts * kCounterStride;
 // Forward launches on meshed scenes (and every pre-filtered launch) trace
 // their photons in an order sorted by cone azimuth: the caller passes an order
-// buffer of min(n, kSortedChunk) uint32 words (sorted must be non-null when
-// forward_sorted holds), and launches of more photons go in chunks of
+// buffer of min(n, kSortedChunk) uint32 words and kBatchCounters counter
+// words (both non-null when forward_sorted holds; the launch zeroes the
+// counters itself), and launches of more photons go in chunks of
 // kSortedChunk.
 constexpr uint64_t kSortedChunk = uint64_t(1) << 24;
 bool forward_sorted(const DevScene &S, const DevSource &src);
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n,
-                          uint64_t first, uint64_t seed, int n_cu, uint32_t *sorted, hipStream_t st);
-// Work counters of the batch kernel: one per id partition, a 128-byte line apart.
-constexpr int kBatchParts = 8;
-constexpr int kCounterStride = 16;
-constexpr int kBatchCounters = kBatchParts * kCounterStride;
+                          uint64_t first, uint64_t seed, int n_cu, uint32_t *sorted, unsigned long long *counter,
+                          hipStream_t st);
 // whole_batch: n is meant to be every photon of the tracks (flag raised if not);
 // counter: kBatchCounters zeroed words
 hipError_t launch_batch(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t seed,

@@ -363,8 +363,11 @@ static_assert(kSortWindow % kSortThreads == 0 && kSortBins % kSortThreads == 0 &
               "sort shape");
 
 __global__ __launch_bounds__(kSortThreads) void sort_photons_kernel(DevScene S, DevSource src, uint64_t n,
-                                                                    uint64_t first, uint64_t seed, uint32_t *sorted) {
+                                                                    uint64_t first, uint64_t seed, uint32_t *sorted,
+                                                                    unsigned long long *counter) {
     __shared__ uint32_t bins[kSortBins];
+    // the trace kernel's claim counters start at zero (it runs next on the stream)
+    if (blockIdx.x == 0 && threadIdx.x < kBatchCounters) counter[threadIdx.x] = 0;
     __shared__ uint16_t slot[kSortWindow];
     __shared__ uint32_t wave_sum[kSortThreads / 64];
     constexpr int per = kSortWindow / kSortThreads;
@@ -418,7 +421,8 @@ __global__ __launch_bounds__(kSortThreads) void sort_photons_kernel(DevScene S, 
 }
 
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
-                                                                uint64_t first, uint64_t seed, const uint32_t *sorted) {
+                                                                uint64_t first, uint64_t seed, const uint32_t *sorted,
+                                                                unsigned long long *counter) {
     extern __shared__ uint32_t lds_stack[];
     uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
     if (!sorted) {
@@ -432,17 +436,22 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
         // The sorted positions are split into one contiguous range per XCD
         // (workgroups are dealt to the eight XCDs round robin), so that an
         // XCD's photons in flight are neighbours in the sorted order and
-        // their outputs lie in few windows.  Within its XCD a block takes
-        // one 256-position slice of each chunk of the range, a different
-        // slice each time: the slices of a window differ in azimuth and so
-        // in cost, and every block should see all of them.
+        // their outputs lie in few windows.  Each wave claims the next 64
+        // positions of its XCD's range from that range's counter (its own
+        // cache line), so the waves of a CU trace neighbouring directions at
+        // once and a wave that drew cheap photons takes more.
         const uint32_t parts = gridDim.x >= 8 ? 8u : 1u;
-        const uint32_t x = blockIdx.x % parts, jb = blockIdx.x / parts, nx = (gridDim.x - x + parts - 1) / parts;
-        const uint64_t span = (n + (uint64_t)parts * kForwardBlock - 1) / ((uint64_t)parts * kForwardBlock) * kForwardBlock;
+        const uint32_t x = blockIdx.x % parts;
+        const uint64_t span = (n + (uint64_t)parts * 64 - 1) / ((uint64_t)parts * 64) * 64;
         const uint64_t lo = (uint64_t)x * span, hi = lo + span < n ? lo + span : n;
-        const uint64_t chunk = (uint64_t)nx * kForwardBlock;
-        for (uint64_t t = 0; lo + t * chunk < hi; ++t) {
-            const uint64_t k = lo + t * chunk + (uint64_t)((jb + t * 41u) % nx) * kForwardBlock + threadIdx.x;
+        unsigned long long *ctr = counter + kCounterStride * x;
+        const int lane = threadIdx.x & 63;
+        while (true) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(ctr, 64ull);
+            const uint32_t c_lo = __shfl((uint32_t)c, 0), c_hi = __shfl((uint32_t)(c >> 32), 0);
+            const uint64_t k = lo + (((uint64_t)c_hi << 32) | c_lo) + (uint64_t)lane;
+            if (k - lane >= hi) break;
             const bool active = k < hi;
             const uint64_t i = active ? sorted[k] : 0;
             int fate = photon_job<true>(S, src, out, active, i, first + i, seed, lane_stack(lds_stack));
@@ -457,17 +466,18 @@ bool forward_sorted(const DevScene &S, const DevSource &src) {
 }
 
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
-                          uint64_t seed, int n_cu, uint32_t *sorted, hipStream_t st) {
+                          uint64_t seed, int n_cu, uint32_t *sorted, unsigned long long *counter, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const bool sort = forward_sorted(S, src);
-    if (sort && !sorted) return hipErrorInvalidValue;
+    if (sort && (!sorted || !counter)) return hipErrorInvalidValue;
     const size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) +
                        kFates * (kForwardBlock / 64) * sizeof(uint32_t);
     // One block per resident slot (registers and LDS decide how many fit on
     // a CU), each looping over its photons; a grid of more blocks runs in
     // waves of blocks, and a partial last wave leaves most CUs idle.  Unsorted
     // (analytic) launches take two blocks per slot, which measured faster
-    // there.  A sorted grid is a multiple of the eight XCDs.
+    // there.  A sorted grid is a multiple of the eight XCDs, each XCD's
+    // blocks claiming from its own counter.
     static const int per_cu = [lds] {
         int b = 0;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, forward_kernel, kForwardBlock, lds) == hipSuccess && b > 0
@@ -491,12 +501,12 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
         if (sort) {
             if (blocks >= 8) blocks -= blocks % 8;
             hipLaunchKernelGGL(sort_photons_kernel, dim3((unsigned)((m + kSortWindow - 1) / kSortWindow)),
-                               dim3(kSortThreads), 0, st, S, src, m, first + off, seed, sorted);
+                               dim3(kSortThreads), 0, st, S, src, m, first + off, seed, sorted, counter);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, o, m,
-                           first + off, seed, (const uint32_t *)(sort ? sorted : nullptr));
+                           first + off, seed, (const uint32_t *)(sort ? sorted : nullptr), counter);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
