@@ -28,10 +28,10 @@ constexpr int kCounterStride = 16;
 constexpr int kBatchCounters = kBatchParts * kCounterStride;
 // Forward launches on meshed scenes (and every pre-filtered launch) trace
 // their photons in an order sorted by cone azimuth: the caller passes an order
-// buffer of min(n, kSortedChunk) uint32 words and kBatchCounters counter
-// words (both non-null when forward_sorted holds; the launch zeroes the
-// counters itself), and launches of more photons go in chunks of
-// kSortedChunk.
+// buffer of min(n, kSortedChunk) uint32 words (non-null when forward_sorted
+// holds), and launches of more photons go in chunks of kSortedChunk.  Every
+// launch takes kBatchCounters counter words for its waves' claims (the
+// launch zeroes them itself).
 constexpr uint64_t kSortedChunk = uint64_t(1) << 24;
 bool forward_sorted(const DevScene &S, const DevSource &src);
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n,

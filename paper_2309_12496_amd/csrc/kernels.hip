@@ -461,54 +461,99 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
     if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
 }
 
+// Large analytic launches: waves claim 64 ids at a time from their XCD's
+// counter in one contiguous range of ids per XCD (as the sorted trace claims
+// sorted positions), so the XCD's waves finish together.
+__global__ __launch_bounds__(kForwardBlock) void forward_ids_kernel(DevScene S, DevSource src, DevOutputs out,
+                                                                    uint64_t n, uint64_t first, uint64_t seed,
+                                                                    unsigned long long *counter) {
+    extern __shared__ uint32_t lds_stack[];
+    uint32_t cnt[kFates] = {0, 0, 0, 0, 0, 0, 0};
+    const uint32_t parts = gridDim.x >= 8 ? 8u : 1u;
+    const uint32_t x = blockIdx.x % parts;
+    const uint64_t span = (n + (uint64_t)parts * 64 - 1) / ((uint64_t)parts * 64) * 64;
+    const uint64_t lo = (uint64_t)x * span, hi = lo + span < n ? lo + span : n;
+    unsigned long long *ctr = counter + kCounterStride * x;
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(ctr, 64ull);
+        const uint32_t c_lo = __shfl((uint32_t)c, 0), c_hi = __shfl((uint32_t)(c >> 32), 0);
+        const uint64_t i = lo + (((uint64_t)c_hi << 32) | c_lo) + (uint64_t)lane;
+        if (i - lane >= hi) break;
+        int fate = photon_job<true>(S, src, out, i < hi, i, first + i, seed, lane_stack(lds_stack));
+        if (out.fate_counts) tally_wave(cnt, fate);
+    }
+    if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
+}
+
 bool forward_sorted(const DevScene &S, const DevSource &src) {
     return (S.has_mesh && src.kind != 2) || src.prefilter;
 }
+
+// How a forward launch hands photons to lanes: a grid-stride loop over the
+// ids (small analytic launches: no extra launch before it), or waves claiming
+// 64 positions at a time, of the sorted order (meshed scenes, pre-filter) or
+// of the ids themselves (large analytic launches).
+enum ForwardMode { kGridStride = 0, kSortedClaims = 1, kIdClaims = 2 };
+
+// Analytic launches of at least this many photons claim their ids (after a
+// fill launch that zeroes the counters); smaller ones are launch bound.
+constexpr uint64_t kIdClaimsMin = uint64_t(1) << 22;
 
 hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutputs &out, uint64_t n, uint64_t first,
                           uint64_t seed, int n_cu, uint32_t *sorted, unsigned long long *counter, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const bool sort = forward_sorted(S, src);
-    if (sort && (!sorted || !counter)) return hipErrorInvalidValue;
+    if (!counter || (sort && !sorted)) return hipErrorInvalidValue;
     const size_t lds = (size_t)kForwardBlock * kStackDepth * sizeof(uint32_t) +
                        kFates * (kForwardBlock / 64) * sizeof(uint32_t);
     // One block per resident slot (registers and LDS decide how many fit on
     // a CU), each looping over its photons; a grid of more blocks runs in
-    // waves of blocks, and a partial last wave leaves most CUs idle.  Unsorted
-    // (analytic) launches take two blocks per slot, which measured faster
-    // there.  A sorted grid is a multiple of the eight XCDs, each XCD's
+    // waves of blocks, and a partial last wave leaves most CUs idle.  The
+    // grid-stride form takes two blocks per slot, which measured faster
+    // there.  A claiming grid is a multiple of the eight XCDs, each XCD's
     // blocks claiming from its own counter.
-    static const int per_cu = [lds] {
+    auto slots = [lds](const void *kernel) {
         int b = 0;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, forward_kernel, kForwardBlock, lds) == hipSuccess && b > 0
-                   ? b
-                   : 4;
-    }();
-    const uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * (uint64_t)per_cu * (sort ? 1u : 2u);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kForwardBlock, lds) == hipSuccess && b > 0 ? b
+                                                                                                                  : 4;
+    };
+    static const int per_cu[3] = {slots((const void *)forward_kernel), slots((const void *)forward_kernel),
+                                  slots((const void *)forward_ids_kernel)};
     // sorted launches go in chunks of at most kSortedChunk photons (the order
     // buffer's size); the outputs of a chunk start at its first photon
     const uint64_t step = sort ? kSortedChunk : n;
     for (uint64_t off = 0; off < n; off += step) {
         const uint64_t m = n - off < step ? n - off : step;
+        const int mode = sort ? kSortedClaims : (m >= kIdClaimsMin ? kIdClaims : kGridStride);
         DevOutputs o = out;   // every per-photon output is optional
         if (o.fate) o.fate += off;
         if (o.pixel) o.pixel += off;
         if (o.hit_xyz) o.hit_xyz += 3 * off;
         if (o.hit_uv) o.hit_uv += 2 * off;
         if (o.hit_time) o.hit_time += off;
+        const uint64_t cap = (uint64_t)(n_cu > 0 ? n_cu : 256) * (uint64_t)per_cu[mode] * (mode == kGridStride ? 2u : 1u);
         uint64_t blocks = (m + kForwardBlock - 1) / kForwardBlock;
         if (blocks > cap) blocks = cap;
-        if (sort) {
-            if (blocks >= 8) blocks -= blocks % 8;
+        if (mode != kGridStride && blocks >= 8) blocks -= blocks % 8;
+        hipError_t e = hipSuccess;
+        if (mode == kSortedClaims) {
+            // the sort also zeroes the claim counters
             hipLaunchKernelGGL(sort_photons_kernel, dim3((unsigned)((m + kSortWindow - 1) / kSortWindow)),
                                dim3(kSortThreads), 0, st, S, src, m, first + off, seed, sorted, counter);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+            e = hipGetLastError();
+        } else if (mode == kIdClaims) {
+            e = launch_fill_u64(counter, kBatchCounters, st);
         }
-        hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(kForwardBlock), lds, st, S, src, o, m,
-                           first + off, seed, (const uint32_t *)(sort ? sorted : nullptr), counter);
-        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        const dim3 grid((unsigned)blocks), block(kForwardBlock);
+        if (mode == kIdClaims)
+            hipLaunchKernelGGL(forward_ids_kernel, grid, block, lds, st, S, src, o, m, first + off, seed, counter);
+        else
+            hipLaunchKernelGGL(forward_kernel, grid, block, lds, st, S, src, o, m, first + off, seed,
+                               (const uint32_t *)(mode == kSortedClaims ? sorted : nullptr), counter);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
 }
