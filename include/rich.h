@@ -343,9 +343,9 @@ rich_status rich_set_mirror_params(rich_scene *s, const float *dev_params, hipSt
  * global hits.  Every output array is the caller's device memory, indexed by
  * g - first_photon_id; NULL skips it.  Asynchronous on `stream`.  On meshed
  * scenes and with the pre-filter the photons are traced in an order sorted
- * by cone azimuth within windows of 8192 ids (a sort kernel runs first, into
- * the stream's order buffer), in launches of at most 2^24 photons; results
- * do not depend on the order.
+ * by cone azimuth within windows of 32,768 ids (8192 with the pre-filter; a
+ * sort kernel runs first, into the stream's order buffer), in launches of
+ * at most 2^24 photons; results do not depend on the order.
  * Errors (synchronous, nothing launched): RICH_EINVAL for NULL scene or
  * source, an unknown source kind, n beta <= 1, a bad table or prefilter
  * material, a hit list without its counter; RICH_ERANGE when the id range

@@ -349,22 +349,30 @@ __device__ __forceinline__ uint32_t regroup_bin(const DevScene &S, const DevSour
 }
 
 // Photons of a forward launch are traced in an order sorted by cone azimuth
-// within windows of kSortWindow ids: sort_photons_kernel counting-sorts each
+// within windows of kWindow ids: sort_photons_kernel counting-sorts each
 // window by the azimuth's uniform (word 0 of the photon's first Philox block;
-// the photons the pre-filter rejects last) into kSortBins bins, and the trace
+// the photons the pre-filter rejects last) into kBins bins, and the trace
 // kernel's waves then take 64 neighbours in that order, whose rays meet the
 // same parts of the scene.  Every photon keeps its id and random numbers and
-// writes its outputs at its id; only the lane that traces it changes.
-constexpr int kSortWindow = 8192;
-constexpr int kSortBins = 1024;
-constexpr int kSortThreads = 256;
-static_assert(kSortWindow % kSortThreads == 0 && kSortBins % kSortThreads == 0 && kSortWindow <= 65536 &&
-                  kSortedChunk % kSortWindow == 0 && kSortedChunk <= (uint64_t(1) << 32),
-              "sort shape");
+// writes its outputs at its id; only the lane that traces it changes.  Wider
+// windows give each wave closer directions but cost the sort more: traced
+// launches sort windows of 32,768 ids, pre-filtered ones (whose trace is
+// short) windows of 8192.
+template <int kWindow, int kBins, int kThreads>
+struct SortShape {
+    static constexpr int window = kWindow, bins = kBins, threads = kThreads;
+    static_assert(kWindow % kThreads == 0 && kBins % kThreads == 0 && kWindow <= 65536 &&
+                      kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 32) && kThreads % 64 == 0,
+                  "sort shape");
+};
+using WideSort = SortShape<32768, 4096, 1024>;
+using NarrowSort = SortShape<8192, 1024, 256>;
 
-__global__ __launch_bounds__(kSortThreads) void sort_photons_kernel(DevScene S, DevSource src, uint64_t n,
-                                                                    uint64_t first, uint64_t seed, uint32_t *sorted,
-                                                                    unsigned long long *counter) {
+template <class Shape>
+__global__ __launch_bounds__(Shape::threads) void sort_photons_kernel(DevScene S, DevSource src, uint64_t n,
+                                                                      uint64_t first, uint64_t seed, uint32_t *sorted,
+                                                                      unsigned long long *counter) {
+    constexpr int kSortWindow = Shape::window, kSortBins = Shape::bins, kSortThreads = Shape::threads;
     __shared__ uint32_t bins[kSortBins];
     // the trace kernel's claim counters start at zero (it runs next on the stream)
     if (blockIdx.x == 0 && threadIdx.x < kBatchCounters) counter[threadIdx.x] = 0;
@@ -540,8 +548,14 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
         hipError_t e = hipSuccess;
         if (mode == kSortedClaims) {
             // the sort also zeroes the claim counters
-            hipLaunchKernelGGL(sort_photons_kernel, dim3((unsigned)((m + kSortWindow - 1) / kSortWindow)),
-                               dim3(kSortThreads), 0, st, S, src, m, first + off, seed, sorted, counter);
+            if (src.prefilter)
+                hipLaunchKernelGGL(sort_photons_kernel<NarrowSort>,
+                                   dim3((unsigned)((m + NarrowSort::window - 1) / NarrowSort::window)),
+                                   dim3(NarrowSort::threads), 0, st, S, src, m, first + off, seed, sorted, counter);
+            else
+                hipLaunchKernelGGL(sort_photons_kernel<WideSort>,
+                                   dim3((unsigned)((m + WideSort::window - 1) / WideSort::window)),
+                                   dim3(WideSort::threads), 0, st, S, src, m, first + off, seed, sorted, counter);
             e = hipGetLastError();
         } else if (mode == kIdClaims) {
             e = launch_fill_u64(counter, kBatchCounters, st);

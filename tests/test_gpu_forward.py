@@ -78,12 +78,12 @@ def test_extreme_ids_and_seeds(R, orc, c1, first, seed):
 
 
 @pytest.mark.parametrize("n,first,prefilter", [(1, 0, False), (63, 7, False), (1025, 1000, False), (3000, 123457, False),
-                                                (8193, 3, False), (1025, 5, True), (2500, 999, True),
-                                                (16385, 77, True)])
+                                                (8193, 3, False), (32769, 11, False), (1025, 5, True),
+                                                (2500, 999, True), (16385, 77, True)])
 def test_meshed_regrouping_at_ragged_sizes(R, orc, c2, n, first, prefilter):
-    """The sorted order (windows of 8192 ids sorted by azimuth, pre-filter rejects last; fewer than
-    eight blocks below 2048 photons) at sizes and offsets that leave partial windows, photon by
-    photon against the oracle."""
+    """The sorted order (windows of 32,768 ids sorted by azimuth, 8192 with the pre-filter, whose
+    rejects go last; fewer than eight blocks below 2048 photons) at sizes and offsets that leave
+    partial windows, photon by photon against the oracle."""
     cfg, gs, os_ = c2
     src = I.with_prefilter(cfg["source"]) if prefilter else cfg["source"]
     out = R.propagate(gs, src, n, cfg["seed"], first_id=first)
