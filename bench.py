@@ -48,14 +48,14 @@ ALU_OPS_PER_PHOTON = 3046.2
 # issued lane slots (inactive lanes of divergent waves included), and
 # SQ_THREAD_CYCLES_VALU / photons = lane operations of active lanes (the
 # counter reads 64 per instruction on a plain copy kernel).
-ISSUED_SLOTS_PER_PHOTON = 5251.4
-ACTIVE_LANE_OPS_PER_PHOTON = 4376.3
+ISSUED_SLOTS_PER_PHOTON = 5266.3
+ACTIVE_LANE_OPS_PER_PHOTON = 4376.0
 # Compulsory HBM bytes per photon: fate 1 + pixel 4 + xyz 12 + uv 8 + arrival time 4 (writes).
 OUT_BYTES_PER_PHOTON = 29.0
 # Bytes per photon out of L2 of the same launch, both kernels: (FETCH_SIZE x 1.9998 + WRITE_SIZE x
 # 1.0) KiB per dispatch, scaled by the 256 MiB copy-kernel calibration (262,144 KiB copied: FETCH_SIZE
 # reads 131,086, WRITE_SIZE 262,144), / 1e7 photons (profiles/forward_kernel_c2_counters.md).
-TRAFFIC_BYTES_PER_PHOTON = ((20478.8 + 206.8) * 1.9998 + 362494.0 + 39063.5) * 1024 / 1e7
+TRAFFIC_BYTES_PER_PHOTON = ((20485.7 + 207.1) * 1.9998 + 389902.0 + 39063.5) * 1024 / 1e7
 
 
 def parse():

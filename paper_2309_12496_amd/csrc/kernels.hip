@@ -365,7 +365,7 @@ struct SortShape {
                       kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 32) && kThreads % 64 == 0,
                   "sort shape");
 };
-using WideSort = SortShape<32768, 4096, 1024>;
+using WideSort = SortShape<32768, 2048, 1024>;
 using NarrowSort = SortShape<8192, 1024, 256>;
 
 template <class Shape>
