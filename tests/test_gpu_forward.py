@@ -118,6 +118,31 @@ def test_split_ranges_are_bit_identical(R, c2):
     assert np.array_equal(to_np(full["histogram"]), to_np(a["histogram"]) + to_np(b["histogram"]))
 
 
+def test_large_analytic_launch_claims_ids(R, orc, c1):
+    """Analytic launches of 2^22 photons or more hand ids to waves through per-XCD claim counters
+    instead of a grid-stride loop: one such call equals, bit for bit, the same ids traced by two
+    smaller (grid-stride) calls, and its last photons match the oracle."""
+    import torch
+    cfg, gs, os_ = c1
+    n = (1 << 22) + 777
+    half = n // 2
+    full = R.propagate(gs, cfg["source"], n, cfg["seed"])
+    a = R.propagate(gs, cfg["source"], half, cfg["seed"], first_id=0)
+    b = R.propagate(gs, cfg["source"], n - half, cfg["seed"], first_id=half)
+    for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time"):
+        fk = to_np(full[k])
+        assert np.array_equal(fk, np.concatenate([to_np(a[k]), to_np(b[k])]), equal_nan=fk.dtype.kind == "f"), k
+    assert np.array_equal(to_np(full["fate_counts"]), to_np(a["fate_counts"]) + to_np(b["fate_counts"]))
+    assert np.array_equal(to_np(full["histogram"]), to_np(a["histogram"]) + to_np(b["histogram"]))
+    m = 5000
+    tail = {k: v[n - m:] for k, v in full.items() if k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time")}
+    compare(tail, orc.propagate(os_, cfg["source"], m, cfg["seed"], first_id=n - m), min_agree=0.999,
+            label="C1 claimed ids, tail")
+    del full, a, b
+    torch.cuda.empty_cache()
+    assert gs.status() == 0
+
+
 def test_sorted_launch_beyond_one_chunk(R, orc, c2):
     """A forward launch on a meshed scene traces its photons in an order sorted by cone azimuth, in
     chunks of 2^24 photons (the order buffer's size).  One call of 2^24 + 4321 photons (two chunks,
