@@ -362,7 +362,8 @@ template <int kWindow, int kBins, int kThreads>
 struct SortShape {
     static constexpr int window = kWindow, bins = kBins, threads = kThreads;
     static_assert(kWindow % kThreads == 0 && kBins % kThreads == 0 && kWindow <= 65536 &&
-                      kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 32) && kThreads % 64 == 0,
+                      kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 32) && kThreads % 64 == 0 &&
+                      kThreads >= kBatchCounters,   // one block zeroes every claim counter
                   "sort shape");
 };
 using WideSort = SortShape<32768, 2048, 1024>;
