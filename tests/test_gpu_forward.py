@@ -311,6 +311,40 @@ def test_c3_batch_subset(R, orc):
     assert gs.status() == 0
 
 
+def test_sorted_forward_in_a_captured_graph(R, c2):
+    """A meshed forward launch (sort kernel, then the trace whose waves claim positions from
+    counters the sort zeroes) captured into a HIP graph after a warm-up call (which grows the
+    stream's order buffer) replays to the eager per-photon outputs every time, with eager work
+    between the replays; fate counts and the histogram accumulate once per replay."""
+    import torch
+    cfg, gs, _ = c2
+    n = 300_001
+    ref = R.propagate(gs, cfg["source"], n, cfg["seed"])
+    s, keep = R.make_source(cfg["source"])
+    t, o = R.alloc_outputs(gs, n)
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        R.rich_propagate(gs.handle, s, n, cfg["seed"], 0, o, cs)   # warm-up: the stream's buffers
+    cs.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        R.rich_propagate(gs.handle, s, n, cfg["seed"], 0, o, cs)
+    for rep in range(3):
+        for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time"):
+            t[k].zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        other = R.propagate(gs, cfg["source"], 1000, cfg["seed"] + rep)   # eager work between replays
+        assert int(to_np(other["fate_counts"]).sum()) == 1000
+        for k in ("fate", "pixel", "hit_xyz", "hit_uv", "hit_time"):
+            a, b = to_np(t[k]), to_np(ref[k])
+            assert np.array_equal(a, b, equal_nan=a.dtype.kind == "f"), (rep, k)
+        assert np.array_equal(to_np(t["fate_counts"]), (rep + 2) * to_np(ref["fate_counts"]))
+        assert np.array_equal(to_np(t["histogram"]), (rep + 2) * to_np(ref["histogram"]))
+    assert gs.status() == 0
+
+
 def test_batch_graph_replay_matches_eager_single_source(R):
     """The batch graph replays to the same result every time, and equals per-track single-source calls."""
     import torch
