@@ -216,27 +216,34 @@ __device__ __forceinline__ void put(T *p, T v) {
 // loads).  The forward kernel gains from it; the batch kernel, held to 128
 // VGPRs, spills the extra scalar state and reads the detector per lane.  The
 // batch kernel (kConstDet false) streams its outputs past L2.
+// rejected: the pre-filter's decision for this photon is already known to be
+// a rejection (the forward sort took it), so it is neither generated nor
+// tested again.
 template <bool kConstDet>
 __device__ __forceinline__ int photon_job(const DevScene &S, const DevSource &src, const DevOutputs &out, bool active,
                                           uint64_t i, uint64_t g, uint64_t seed, uint32_t *stk,
-                                          int track = -1) {
+                                          int track = -1, bool rejected = false) {
     PathEnd end;
     end.fate = -1;
     end.pixel = -1;
     if (active) {
-        Photon ph = make_photon(src, seed, g, i, true, track);
-        NoRecord rec;
-        auto run = [&](const auto &det) {
-            if (!src.prefilter) {
-                propagate(S, det, ph, seed, g, stk, end, rec);
-            } else if (prefilter_keep(S, det, src, ph, seed, g)) {
-                propagate(S, det, ph, seed, g, stk, end, rec, false);
-            } else {
-                end.fate = kPrefiltered;
-            }
-        };
-        if constexpr (kConstDet) run(cref(*S.det));
-        else run(*S.det);
+        if (rejected) {
+            end.fate = kPrefiltered;
+        } else {
+            Photon ph = make_photon(src, seed, g, i, true, track);
+            NoRecord rec;
+            auto run = [&](const auto &det) {
+                if (!src.prefilter) {
+                    propagate(S, det, ph, seed, g, stk, end, rec);
+                } else if (prefilter_keep(S, det, src, ph, seed, g)) {
+                    propagate(S, det, ph, seed, g, stk, end, rec, false);
+                } else {
+                    end.fate = kPrefiltered;
+                }
+            };
+            if constexpr (kConstDet) run(cref(*S.det));
+            else run(*S.det);
+        }
         bool on_det = end.fate == kDetected || end.fate == kQeRejected;
         constexpr bool kStream = !kConstDet;
         const float nan = __builtin_nanf("");
@@ -362,7 +369,7 @@ template <int kWindow, int kBins, int kThreads>
 struct SortShape {
     static constexpr int window = kWindow, bins = kBins, threads = kThreads;
     static_assert(kWindow % kThreads == 0 && kBins % kThreads == 0 && kWindow <= 65536 &&
-                      kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 32) && kThreads % 64 == 0 &&
+                      kSortedChunk % kWindow == 0 && kSortedChunk <= (uint64_t(1) << 31) && kThreads % 64 == 0 &&
                       kThreads >= kBatchCounters,   // one block zeroes every claim counter
                   "sort shape");
 };
@@ -425,10 +432,18 @@ __global__ __launch_bounds__(Shape::threads) void sort_photons_kernel(DevScene S
         const uint32_t l = (uint32_t)(j * kSortThreads) + threadIdx.x;
         if (l < m) slot[bins[key[j] & 0xFFFFu] + (key[j] >> 16)] = (uint16_t)l;
     }
+    // photons the pre-filter rejects fill the window's last bin (when the
+    // wavelength alone decides): their sorted entries carry the top bit, and
+    // the trace writes their fate without generating them again
+    const uint32_t rejected_from = src.prefilter && src.n_disp == 0 && src.kind != 2 ? bins[kSortBins - 1] : m;
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < m; q += kSortThreads) sorted[w0 + q] = (uint32_t)(w0 + slot[q]);
+    for (uint32_t q = threadIdx.x; q < m; q += kSortThreads)
+        sorted[w0 + q] = (uint32_t)(w0 + slot[q]) | (q >= rejected_from ? 0x80000000u : 0u);
 }
 
+// kRejectBit: sorted entries with the top bit set are photons the sort
+// already saw the pre-filter reject (pre-filtered launches only).
+template <bool kRejectBit>
 __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevSource src, DevOutputs out, uint64_t n,
                                                                 uint64_t first, uint64_t seed, const uint32_t *sorted,
                                                                 unsigned long long *counter) {
@@ -462,9 +477,17 @@ __global__ __launch_bounds__(kForwardBlock) void forward_kernel(DevScene S, DevS
             const uint64_t k = lo + (((uint64_t)c_hi << 32) | c_lo) + (uint64_t)lane;
             if (k - lane >= hi) break;
             const bool active = k < hi;
-            const uint64_t i = active ? sorted[k] : 0;
-            int fate = photon_job<true>(S, src, out, active, i, first + i, seed, lane_stack(lds_stack));
-            if (out.fate_counts) tally_wave(cnt, fate);
+            if constexpr (kRejectBit) {
+                const uint32_t e = active ? sorted[k] : 0u;
+                const uint64_t i = e & 0x7FFFFFFFu;
+                int fate = photon_job<true>(S, src, out, active, i, first + i, seed, lane_stack(lds_stack), -1,
+                                            (e >> 31) != 0u);
+                if (out.fate_counts) tally_wave(cnt, fate);
+            } else {
+                const uint64_t i = active ? sorted[k] : 0;
+                int fate = photon_job<true>(S, src, out, active, i, first + i, seed, lane_stack(lds_stack));
+                if (out.fate_counts) tally_wave(cnt, fate);
+            }
         }
     }
     if (out.fate_counts) flush_tally(S, out, cnt, lds_stack + (size_t)blockDim.x * kStackDepth);
@@ -528,7 +551,7 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kForwardBlock, lds) == hipSuccess && b > 0 ? b
                                                                                                                   : 4;
     };
-    static const int per_cu[3] = {slots((const void *)forward_kernel), slots((const void *)forward_kernel),
+    static const int per_cu[3] = {slots((const void *)forward_kernel<false>), slots((const void *)forward_kernel<false>),
                                   slots((const void *)forward_ids_kernel)};
     // sorted launches go in chunks of at most kSortedChunk photons (the order
     // buffer's size); the outputs of a chunk start at its first photon
@@ -565,8 +588,11 @@ hipError_t launch_forward(const DevScene &S, const DevSource &src, const DevOutp
         const dim3 grid((unsigned)blocks), block(kForwardBlock);
         if (mode == kIdClaims)
             hipLaunchKernelGGL(forward_ids_kernel, grid, block, lds, st, S, src, o, m, first + off, seed, counter);
+        else if (mode == kSortedClaims && src.prefilter && src.n_disp == 0 && src.kind != 2)
+            hipLaunchKernelGGL(forward_kernel<true>, grid, block, lds, st, S, src, o, m, first + off, seed,
+                               (const uint32_t *)sorted, counter);
         else
-            hipLaunchKernelGGL(forward_kernel, grid, block, lds, st, S, src, o, m, first + off, seed,
+            hipLaunchKernelGGL(forward_kernel<false>, grid, block, lds, st, S, src, o, m, first + off, seed,
                                (const uint32_t *)(mode == kSortedClaims ? sorted : nullptr), counter);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
