@@ -374,7 +374,7 @@ struct SortShape {
                   "sort shape");
 };
 using WideSort = SortShape<32768, 2048, 1024>;
-using NarrowSort = SortShape<8192, 1024, 256>;
+using NarrowSort = SortShape<8192, 1024, 512>;
 
 template <class Shape>
 __global__ __launch_bounds__(Shape::threads) void sort_photons_kernel(DevScene S, DevSource src, uint64_t n,
